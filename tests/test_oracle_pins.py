@@ -1,0 +1,409 @@
+"""Pins of the CPU oracle against facts fixed by mathematics and physics.
+
+Each test checks the oracle against something other than itself: a closed-form
+solution, an identity, a conservation law, an independent solver (Gibbs
+minimisation, explicit RK4) or the published properties of the Rodas4
+coefficient table.  None of these tests need a GPU.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import Oracle
+from paper_2011_07978_amd import synth
+from tests.mini_mechs import P_ATM, RU_ERG, isomerisation
+
+
+@pytest.fixture(scope="module")
+def small():
+    return Oracle(synth.mechanism("small"))
+
+
+@pytest.fixture(scope="module")
+def m53():
+    return Oracle(synth.mechanism("mech53"))
+
+
+def _state(field, i):
+    return np.concatenate([[field.T[i]], field.Y[:, i]])
+
+
+# --------------------------------------------------------------------- thermo
+def test_thermo_identities(small):
+    """cp = dH/dT and dS/dT = cp/T by central differences (NASA-7 identities)."""
+    for T in (300.0, 800.0, 1500.0, 2600.0):
+        d = 1e-3
+        cp, h, s = small.thermo(T)
+        _, hp, sp = small.thermo(T + d)
+        _, hm, sm = small.thermo(T - d)
+        H = lambda hrt, t: hrt * t  # H/R
+        dHdT = (H(hp, T + d) - H(hm, T - d)) / (2 * d)
+        np.testing.assert_allclose(dHdT, cp, rtol=1e-8)
+        np.testing.assert_allclose((sp - sm) / (2 * d), cp / T, rtol=1e-7)
+        assert np.all(cp > 0)
+
+
+def test_cp_positive_on_range():
+    for name in ("small", "mech53", "mech130"):
+        o = Oracle(synth.mechanism(name))
+        for T in np.linspace(200.0, 10000.0, 60):
+            assert np.all(o.thermo(T)[0] > 0), (name, T)
+
+
+# ------------------------------------------------------------------- kinetics
+@pytest.mark.parametrize("name", ["small", "mech53"])
+def test_element_and_mass_conservation_of_rates(name):
+    mech = synth.mechanism(name)
+    o = Oracle(mech)
+    f = synth.field_small(8) if name == "small" else synth.field_bimodal("mech53", 2000, shuffle=True)
+    for i in range(6):
+        kf, kr, q, om = o.kinetics(f.T[i], f.p[i], f.Y[:, i])
+        scale = np.abs(q).max() * 10
+        # element balance sum_k a_ek omega_k = 0 and mass sum_k W_k omega_k = 0
+        np.testing.assert_allclose(mech.composition.T.astype(float) @ om, 0.0, atol=1e-12 * scale)
+        np.testing.assert_allclose(mech.W @ om, 0.0, atol=1e-12 * scale * mech.W.max())
+        y = _state(f, i)
+        fy = o.rhs(f.p[i], y)
+        assert abs(fy[1:].sum()) <= 1e-12 * np.abs(fy[1:]).max() * 10
+
+
+@pytest.mark.parametrize("name", ["small", "mech53"])
+def test_energy_equation_conserves_enthalpy(name):
+    """A small step along f(y) leaves h(T, Y) unchanged to second order."""
+    o = Oracle(synth.mechanism(name))
+    f = synth.field_small(8) if name == "small" else synth.field_bimodal("mech53", 2000, shuffle=True)
+    for i in range(4):
+        y = _state(f, i)
+        fy = o.rhs(f.p[i], y)
+        eps = 1e-4 * y[0] / max(abs(fy[0]), 1e-300)
+        eps = min(eps, 1e-4 / max(np.abs(fy[1:]).max(), 1e-300))
+        hp = o.enthalpy(y[0] + eps * fy[0], y[1:] + eps * fy[1:])
+        hm = o.enthalpy(y[0] - eps * fy[0], y[1:] - eps * fy[1:])
+        h0 = o.enthalpy(y[0], y[1:])
+        dh = (hp - hm) / (2 * eps)   # d h / dt along the solution
+        scale = o.cp(y[0], y[1:]) * abs(fy[0]) + 1e-300
+        assert abs(dh) <= 1e-6 * scale + 1e-9 * abs(h0) / eps
+
+
+def test_detailed_balance_ratio(small):
+    """k_f / k_r equals the equilibrium constant built from the Gibbs energies."""
+    mech = small.mech
+    for T in (600.0, 1400.0, 2500.0):
+        kf, kr, q, om = small.kinetics(T, P_ATM, np.full(mech.n_species, 0.1))
+        cp, h, s = small.thermo(T)
+        g = h - s
+        for j in range(mech.n_reactions):
+            rs = [k for k in mech.reactants[j] if k >= 0]
+            ps = [k for k in mech.products[j] if k >= 0]
+            dG = g[ps].sum() - g[rs].sum()
+            dnu = len(ps) - len(rs)
+            lnKc = -dG + dnu * np.log(P_ATM / (RU_ERG * T))
+            assert abs(np.log(kf[j] / kr[j]) - lnKc) <= 1e-9 * max(1.0, abs(lnKc))
+
+
+# --------------------------------------------------------------- closed forms
+@pytest.mark.parametrize("tb", [False, True])
+def test_isomerisation_closed_form(tb):
+    """A <=> B: Y_A(t) = Y_eq + (Y_A0 - Y_eq) exp(-(k + k') t) exactly."""
+    T, p, dt = 1000.0, P_ATM, 1e-6
+    A = 3e6 if not tb else 3e6 / (P_ATM / (RU_ERG * T))   # k [1/s] either way
+    eff = {2: 2.0} if tb else None
+    mech = isomerisation(A=A, delta_a7=1.3, third_body=tb, eff=eff)
+    o = Oracle(mech)
+    Y0 = np.array([0.5, 0.1, 0.4])
+    W = mech.W
+    if tb:
+        # [M] = sum_k alpha_k C_k = (p / R T) (X_A + X_B + 2 X_D)
+        X = (Y0 / W) / (Y0 / W).sum()
+        k = A * (P_ATM / (RU_ERG * T)) * (X[0] + X[1] + 2.0 * X[2])
+    else:
+        k = A
+    kp = k * np.exp(-1.3)
+    y, h, st = o.integrate_cell(p, np.r_[T, Y0], dt)
+    assert st.status == 0 and st.n_accept > 3
+    tot = Y0[0] + Y0[1]
+    Yeq = tot * kp / (k + kp)
+    exact = Yeq + (Y0[0] - Yeq) * np.exp(-(k + kp) * dt)
+    assert abs(y[1] - exact) <= 10 * 1e-8 * abs(exact) + 1e-12
+    assert abs(y[0] - T) <= 1e-9 * T                 # zero reaction enthalpy
+    assert abs(y[1:].sum() - 1.0) <= 1e-14
+
+
+def test_exponential_relaxation():
+    """A -> B with Kc = e^40: Y_A = Y_A0 exp(-k t) to within 10 rtol."""
+    mech = isomerisation(A=2e7, delta_a7=40.0)
+    o = Oracle(mech)
+    Y0 = np.array([0.7, 0.0, 0.3])
+    for dt in (1e-7, 1e-6, 1e-5):
+        y, h, st = o.integrate_cell(P_ATM, np.r_[900.0, Y0], dt)
+        exact = 0.7 * np.exp(-2e7 * dt)
+        assert abs(y[1] - exact) <= 10 * 1e-8 * 0.7, (dt, y[1], exact)
+
+
+# ------------------------------------------------------------ Rodas4 tableau
+def _rodas_original():
+    a, c, g = oracle.rodas4_coefficients()
+    s = 6
+    Ginv = np.diag(np.full(s, 1.0 / g)) - c
+    Gam = np.linalg.inv(Ginv)
+    alpha = a @ Gam
+    m = np.r_[a[5, :5], 1.0]           # y_new = y + sum a_6j u_j + u_6
+    mhat = np.r_[a[5, :5], 0.0]        # embedded: stage-6 input
+    return alpha, Gam, m @ Gam, mhat @ Gam, g
+
+
+def _order_conditions(b, alpha, Gam, g, order):
+    beta = alpha + Gam
+    Bs = np.tril(beta, -1)             # beta_ij, j < i
+    a_i = alpha.sum(1)
+    bp = Bs.sum(1)                      # beta'_i
+    conds = [(b.sum(), 1.0), (b @ bp, 0.5 - g), (b @ a_i ** 2, 1 / 3),
+             (b @ (Bs @ bp), 1 / 6 - g + g * g)]
+    if order >= 4:
+        conds += [(b @ a_i ** 3, 0.25), (b @ (a_i * (alpha @ bp)), 1 / 8 - g / 3),
+                  (b @ (Bs @ a_i ** 2), 1 / 12 - g / 3),
+                  (b @ (Bs @ (Bs @ bp)), 1 / 24 - g / 2 + 1.5 * g * g - g ** 3)]
+    return conds
+
+
+def test_rodas4_order_conditions():
+    alpha, Gam, b, bhat, g = _rodas_original()
+    for lhs, rhs in _order_conditions(b, alpha, Gam, g, 4):
+        assert abs(lhs - rhs) <= 2e-14, (lhs, rhs)
+    for lhs, rhs in _order_conditions(bhat, alpha, Gam, g, 3):
+        assert abs(lhs - rhs) <= 2e-14, (lhs, rhs)
+    # the embedded method is not of order 4 (the estimate is meaningful)
+    worst = max(abs(l - r) for l, r in _order_conditions(bhat, alpha, Gam, g, 4)[4:])
+    assert worst > 1e-6
+
+
+def _stability(z, b, alpha, Gam):
+    B = alpha + Gam
+    s = len(b)
+    return 1.0 + z * b @ np.linalg.solve(np.eye(s) - z * B, np.ones(s))
+
+
+def test_rodas4_L_stable_and_stiffly_accurate():
+    alpha, Gam, b, bhat, g = _rodas_original()
+    B = alpha + Gam
+    assert abs(1.0 - b @ np.linalg.solve(B, np.ones(6))) <= 1e-13          # R(inf) = 0
+    assert abs(1.0 - bhat @ np.linalg.solve(B, np.ones(6))) <= 1e-13       # embedded too
+    np.testing.assert_allclose(B[5, :], b, atol=1e-13)                    # stiffly accurate
+    for z in (-1e-3, -1.0, -10.0, -1e3, -1e6, 1e-3j - 5, 40j - 0.1):
+        assert abs(_stability(z, b, alpha, Gam)) <= 1.0 + 1e-12
+
+
+def test_single_step_applies_stability_function():
+    """With exact J on linear kinetics one step maps the deviation by R(-(k+k')h)."""
+    mech = isomerisation(A=5e6, delta_a7=0.7)
+    o = Oracle(mech)
+    alpha, Gam, b, bhat, g = _rodas_original()
+    y0 = np.r_[1200.0, 0.6, 0.1, 0.3]
+    k = 5e6
+    kp = k * np.exp(-0.7)
+    Yeq = 0.7 * kp / (k + kp)
+    for h in (1e-8, 1e-7, 1e-6, 1e-4):
+        yn, err, rc = o.rodas4_step(P_ATM, y0, h)
+        R = _stability(-(k + kp) * h, b, alpha, Gam)
+        assert abs((yn[1] - Yeq) - R * (0.6 - Yeq)) <= 1e-13
+        Rh = _stability(-(k + kp) * h, bhat, alpha, Gam)
+        assert abs(err[1] - (R - Rh) * (0.6 - Yeq)) <= 1e-13
+
+
+# ---------------------------------------------------------------- Jacobian
+@pytest.mark.parametrize("name", ["small", "mech53"])
+def test_analytic_jacobian_matches_complex_step(name):
+    mech = synth.mechanism(name)
+    o = Oracle(mech)
+    f = synth.field_small(16) if name == "small" else synth.field_bimodal("mech53", 4000, shuffle=True)
+    for i in range(5):
+        y = _state(f, i)
+        J = o.jac(f.p[i], y)
+        Jc = o.jac_cs(f.p[i], y)
+        scale = np.abs(Jc).max(axis=1, keepdims=True)        # per row
+        diff = np.abs(J - Jc)
+        assert np.all(diff[scale[:, 0] == 0] == 0)            # species in no reaction
+        scale = np.where(scale > 0, scale, 1.0)
+        assert np.max(diff / scale) <= 1e-12
+
+
+def test_complex_step_matches_finite_differences(small):
+    f = synth.field_small(4)
+    y = _state(f, 1)
+    Jc = small.jac_cs(f.p[1], y)
+    rng = np.random.default_rng(3)
+    v = rng.standard_normal(y.size) * np.abs(y) * 1e-3
+    eps = 1e-4
+    fd = (small.rhs(f.p[1], y + eps * v) - small.rhs(f.p[1], y - eps * v)) / (2 * eps)
+    np.testing.assert_allclose(fd, Jc @ v, rtol=1e-5, atol=1e-7 * np.abs(Jc @ v).max())
+    fr, fi = small.rhs_cs_dir(f.p[1], y, v)
+    np.testing.assert_allclose(fr, small.rhs(f.p[1], y), rtol=1e-14, atol=0)
+
+
+# ---------------------------------------------------------------------- LU
+def test_lu_residual_and_solve():
+    rng = np.random.default_rng(0)
+    for n in (1, 5, 11, 54, 131):
+        A = rng.standard_normal((n, n))
+        A[0, 0] = 0.0 if n > 1 else A[0, 0]     # forces a pivot
+        LU, piv, rc = oracle.lu(A)
+        assert rc == 0
+        L = np.tril(LU, -1) + np.eye(n)
+        U = np.triu(LU)
+        PA = A.copy()
+        for k in range(n):
+            PA[[k, piv[k]]] = PA[[piv[k], k]]
+        assert np.abs(PA - L @ U).max() <= 1e-14 * n * np.abs(A).max() * 10
+        x = rng.standard_normal(n)
+        xs = oracle.lu_solve(LU, piv, A @ x)
+        assert np.abs(xs - x).max() <= 1e-12 * np.linalg.cond(A)
+
+
+def test_lu_tie_break_and_singular():
+    A = np.array([[1.0, 2.0], [-1.0, 3.0]])
+    LU, piv, rc = oracle.lu(A)
+    assert rc == 0 and piv[0] == 0                # |1| == |-1|: lowest row wins
+    LU, piv, rc = oracle.lu(np.zeros((3, 3)))
+    assert rc == 1
+
+
+# --------------------------------------------------------------- invariants
+def test_invariants_after_integration(m53):
+    mech = m53.mech
+    f = synth.field_bimodal("mech53", 4000, shuffle=True)
+    sub = synth.subsample(f, np.arange(12))
+    T, Y, h, st, na, nr = m53.integrate_batch(sub.T, sub.p, sub.Y, sub.dt, threads=8)
+    assert np.all(st == 0)
+    np.testing.assert_allclose(Y.sum(0), 1.0, atol=1e-13)
+    E0 = (mech.composition.T / mech.W) @ sub.Y
+    E1 = (mech.composition.T / mech.W) @ Y
+    np.testing.assert_allclose(E1, E0, rtol=1e-12, atol=1e-15)
+    for i in range(sub.n_cells):
+        h0 = m53.enthalpy(sub.T[i], sub.Y[:, i])
+        h1 = m53.enthalpy(T[i], Y[:, i])
+        cpT = m53.cp(sub.T[i], sub.Y[:, i]) * sub.T[i]
+        assert abs(h1 - h0) <= 1e-6 * max(abs(h0), cpT)
+
+
+def test_tolerance_convergence(small):
+    f = synth.field_small(16)
+    sub = synth.subsample(f, np.arange(6))
+    ref = small.integrate_batch(sub.T, sub.p, sub.Y, sub.dt, rtol=1e-12, atol=1e-16)
+    errs = []
+    for rtol in (1e-6, 1e-8, 1e-10):
+        out = small.integrate_batch(sub.T, sub.p, sub.Y, sub.dt, rtol=rtol, atol=rtol * 1e-4)
+        errs.append(np.abs(out[0] - ref[0]).max() / ref[0].max())
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[1] <= 1e-6 and errs[2] <= 1e-8
+
+
+# -------------------------------------------------------------- brute force
+def test_matches_brute_force_rk4(small):
+    f = synth.field_small(64)
+    # pick the cell whose Jacobian has the smallest spectral radius
+    best, lam = None, np.inf
+    for i in range(64):
+        y = _state(f, i)
+        ev = np.abs(np.linalg.eigvals(small.jac(f.p[i], y))).max()
+        if ev < lam:
+            best, lam = i, ev
+    y0 = _state(f, best)
+    t_end = min(f.dt, 1.5e6 / lam * 1e-3)          # about 1.5e6 RK4 steps
+    n = int(np.ceil(t_end * lam / 1e-3))
+    y_rk = small.rk4(f.p[best], y0, t_end, n)
+    y_rk2 = small.rk4(f.p[best], y0, t_end, n // 2)
+    rich_T = abs(y_rk[0] - y_rk2[0]) / 15.0 / y_rk[0]
+    rich_Y = np.abs(y_rk[1:] - y_rk2[1:]).max() / 15.0
+    y_ro, h, st = small.integrate_cell(f.p[best], y0, t_end, rtol=1e-10, atol=1e-14)
+    assert st.status == 0
+    assert rich_T < 1e-12 and rich_Y < 1e-11     # RK4 error far below the test bound
+    assert abs(y_ro[0] - y_rk[0]) <= 1e-8 * y_rk[0]
+    assert np.abs(y_ro[1:] - y_rk[1:]).max() <= 1e-8
+
+
+# ----------------------------------------------------- Gibbs equilibrium
+def _left_null_space(M, tol=1e-10):
+    u, s, vt = np.linalg.svd(M)
+    rank = int((s > tol * s.max()).sum())
+    return u[:, rank:].T        # rows c with c^T M = 0
+
+
+def _gibbs_equilibrium(g, p, y0, A):
+    """Minimise G/RT = sum y_k (g_k + ln(y_k/n) + ln(p/p_atm)) subject to A y = A y0
+    by Newton on the element potentials (y in mol/g).  Independent of kinetics."""
+    b = A @ y0
+    lnp = np.log(p / P_ATM)
+    n = y0.sum()
+    # initial potentials: least-squares fit of the stationarity condition
+    lam = np.linalg.lstsq(A.T, np.log(np.maximum(y0, 1e-300) / n) + g + lnp, rcond=None)[0]
+    lnn = np.log(n)
+    for it in range(200):
+        y = np.exp(lnn + A.T @ lam - g - lnp)
+        F = np.r_[A @ y - b, y.sum() - np.exp(lnn)]
+        Jm = np.zeros((A.shape[0] + 1, A.shape[0] + 1))
+        Jm[:-1, :-1] = (A * y) @ A.T
+        Jm[:-1, -1] = A @ y
+        Jm[-1, :-1] = A @ y
+        Jm[-1, -1] = y.sum() - np.exp(lnn)
+        d = np.linalg.solve(Jm, -F)
+        step = min(1.0, 2.0 / max(1e-300, np.abs(d).max()))
+        lam += step * d[:-1]
+        lnn += step * d[-1]
+        if np.abs(d).max() < 1e-14:
+            break
+    return np.exp(lnn + A.T @ lam - g - lnp)
+
+
+def test_long_time_reaches_gibbs_equilibrium(small):
+    mech = small.mech
+    N = mech.n_species
+    nu = np.zeros((N, mech.n_reactions))
+    for j in range(mech.n_reactions):
+        for k in mech.reactants[j]:
+            if k >= 0:
+                nu[k, j] -= 1
+        for k in mech.products[j]:
+            if k >= 0:
+                nu[k, j] += 1
+    A = _left_null_space(nu)          # kinetically conserved combinations
+    f = synth.field_small(8)
+    for i in (0, 3):
+        y0 = _state(f, i)
+        y0[0] = 2400.0
+        h0 = small.enthalpy(y0[0], y0[1:])
+        y, h, st = small.integrate_cell(P_ATM, y0, 1e8, rtol=1e-11, atol=1e-20, max_steps=200000,
+                                        hmin_frac=1e-40)
+        assert st.status == 0
+        T_eq = y[0]
+        # energy conserved -> (T, Y) is the constant-(h, p) state
+        assert abs(small.enthalpy(T_eq, y[1:]) - h0) <= 1e-8 * abs(h0) + 1e-8 * small.cp(T_eq, y[1:]) * T_eq
+        cp, hh, s = small.thermo(T_eq)
+        g = hh - s
+        moles = _gibbs_equilibrium(g, P_ATM, y[1:] / mech.W, A)
+        Yg = moles * mech.W
+        assert np.abs(Yg - y[1:]).max() <= 1e-9
+        # every reaction in detailed balance
+        kf, kr, q, om = small.kinetics(T_eq, P_ATM, y[1:])
+        rho = small.density(T_eq, P_ATM, y[1:])
+        Cc = rho * y[1:] / mech.W
+        for j in range(mech.n_reactions):
+            rf = kf[j] * np.prod([Cc[k] for k in mech.reactants[j] if k >= 0])
+            rr = kr[j] * np.prod([Cc[k] for k in mech.products[j] if k >= 0])
+            assert abs(np.log(rf) - np.log(rr)) <= 1e-6
+
+
+# ------------------------------------------------------------ failure codes
+def test_status_codes(small):
+    f = synth.field_small(4)
+    y = _state(f, 0)
+    _, _, st = small.integrate_cell(P_ATM, np.r_[-5.0, y[1:]], 1e-6)
+    assert st.status == 4
+    yb = y.copy(); yb[3] = np.nan
+    _, _, st = small.integrate_cell(P_ATM, yb, 1e-6)
+    assert st.status == 4
+    _, _, st = small.integrate_cell(0.0, y, 1e-6)
+    assert st.status == 4
+    _, _, st = small.integrate_cell(P_ATM, y, 1e-6, max_steps=1)
+    assert st.status == 1
+    _, _, st = small.integrate_cell(P_ATM, y, 1e-6, hmin_frac=0.5)
+    assert st.status == 2
