@@ -1,0 +1,199 @@
+/*
+ * libchem — per-cell stiff chemistry integration on one MI355X (gfx950).
+ *
+ * The paper (DLBFoam, arXiv 2011.07978) splits a reacting-flow step so that
+ * every finite-volume cell's chemistry becomes an independent stiff reactor
+ * ODE dPhi/dt = f(Phi) over one flow time step (Sec. 1, Sec. 2.1).  It balances
+ * these per-cell problems across MPI ranks (Sec. 2.2, Algorithm 1) and lets
+ * cells whose mixture fraction (and optionally temperature) lies within
+ * tolerance of a reference cell reuse the reference's solution (Sec. 2.3).
+ * This library is that hot path on one GPU: reference mapping, an on-device
+ * work queue ordered heavy-first by the previous call's per-cell cost (the
+ * analogue of the paper's CPU-time load measure), and FP64 Rosenbrock (Rodas4)
+ * integration with an analytic Jacobian and batched LU, all in hand-written
+ * HIP kernels.
+ *
+ * Conventions for every entry point:
+ *  - Array arguments marked "device" are device pointers (HIP global memory,
+ *    FP64 unless stated), contiguous, owned by the caller, and must stay valid
+ *    until the work enqueued on the context's stream has finished.
+ *  - Species mass fractions are species-major: Y[k * n_cells + i] is species k
+ *    of cell i.
+ *  - Work is enqueued asynchronously on the context's HIP stream.  A non-NULL
+ *    host `stats` argument makes the call wait for its own work.
+ *  - Units: CGS.  T in K, p in dyn/cm^2, dt and h in s, molar masses in g/mol,
+ *    pre-exponential factors in (cm^3/mol)^(order-1)/s, Ea in J/mol.
+ *  - Return value: 0 success; negative CHEM_E_* error (nothing was written);
+ *    for chem_integrate a positive k means k cells failed and their status
+ *    bytes say why.  chem_last_error() gives a message for the last failure.
+ *  - One context per host thread; calls on one context are not re-entrant.
+ */
+#ifndef LIBCHEM_CHEM_H
+#define LIBCHEM_CHEM_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CHEM_OK = 0,
+    CHEM_E_INVALID_ARG = -1,
+    CHEM_E_NO_MECHANISM = -2,
+    CHEM_E_HIP = -3,
+    CHEM_E_OOM = -4,
+    CHEM_E_UNIMPL = -5,
+    CHEM_E_CAPTURE_UNSAFE = -6,
+    CHEM_E_BAD_MECHANISM = -7
+};
+
+/* per-cell status bytes written by chem_integrate */
+enum {
+    CHEM_CELL_OK = 0,
+    CHEM_CELL_MAX_STEPS = 1,   /* attempted-step limit reached */
+    CHEM_CELL_H_UNDERFLOW = 2, /* step fell below hmin_frac * dt */
+    CHEM_CELL_NONFINITE = 3,   /* accepted state not finite */
+    CHEM_CELL_BAD_INPUT = 4,   /* T <= 0, p <= 0 or non-finite input; cell untouched */
+    CHEM_CELL_MAPPED = 5       /* cell took the reference's increment */
+};
+
+/* scheduling of cells onto wavefronts */
+enum {
+    CHEM_SCHED_PLAIN = 0,  /* one static launch, cell i on workgroup i */
+    CHEM_SCHED_QUEUE = 1   /* persistent kernel, atomic work queue + stealing */
+};
+
+typedef struct chem_ctx chem_ctx;
+
+/* Mechanism description (host arrays, deep-copied by chem_set_mechanism).
+ * Reactions are reversible mass-action reactions with 1-2 reactant and 1-3
+ * product slots (-1 = unused slot; a species may fill two slots); reverse rate
+ * constants follow from equilibrium constants of the NASA-7 style single-range
+ * thermodynamics.  Third-body reactions multiply the rate by
+ * [M] = sum_k alpha_k C_k with alpha_k = 1 unless listed in eff_*. */
+typedef struct {
+    int32_t n_elements, n_species, n_reactions;
+    const double *elem_mass;     /* [E] g/mol */
+    const int32_t *composition;  /* [N*E] atom counts, row = species */
+    const double *W;             /* [N] molar masses, must equal sum_e a_ek m_e */
+    const double *nasa;          /* [N*7] a1..a7: cp/R = a1 + a2 T + ... + a5 T^4,
+                                    H/RT adds a6/T, S/R adds a7 */
+    const int32_t *reactants;    /* [R*2] species indices, -1 padded */
+    const int32_t *products;     /* [R*3] species indices, -1 padded */
+    const double *A;             /* [R] pre-exponential factor (> 0) */
+    const double *b;             /* [R] temperature exponent */
+    const double *Ea;            /* [R] activation energy J/mol */
+    const int32_t *third_body;   /* [R] 0/1 */
+    int32_t n_eff;               /* number of non-default efficiencies */
+    const int32_t *eff_reaction; /* [n_eff] reaction index (must be third-body) */
+    const int32_t *eff_species;  /* [n_eff] species index */
+    const double *eff_value;     /* [n_eff] efficiency alpha */
+} chem_mech_desc;
+
+typedef struct {
+    double rtol;          /* relative tolerance (default 1e-8) */
+    double atol;          /* absolute tolerance (default 1e-12) */
+    int32_t max_steps;    /* attempted-step limit per cell and call (default 100000) */
+    double hmin_frac;     /* fail when h < hmin_frac * dt (default 1e-14) */
+    int32_t schedule;     /* CHEM_SCHED_PLAIN or CHEM_SCHED_QUEUE (default QUEUE) */
+    int32_t queue_chunk;  /* cells per atomic grab; 0 = tuned value (default 0) */
+    int32_t slots_per_cu; /* persistent workgroups per CU; 0 = tuned value */
+    int32_t order_by_cost;/* 1: heavy-first queue order from `cost` (default 1) */
+} chem_options;
+
+/* Reference-mapping parameters (Sec. 2.3).  Mixture fraction
+ * Z = (beta - beta_ox) / (beta_fuel - beta_ox), beta(Y) = sum_k w_k Y_k with
+ * w_k = sum_e c_e a_ek m_e / W_k and c_e = (Z_e(Y_fuel) - Z_e(Y_ox)) / m_e,
+ * Z_e(Y) = sum_k a_ek m_e Y_k / W_k (a Bilger-type coupling of all elements). */
+typedef struct {
+    double Z_tol;          /* cells with Z < Z_tol are candidates (strict) */
+    double T_tol;          /* and, if use_T, |T - T_ref| < T_tol (strict) */
+    int32_t use_T;
+    const double *Y_fuel;  /* host [N] fuel-stream mass fractions */
+    const double *Y_ox;    /* host [N] oxidiser-stream mass fractions */
+} chem_map_params;
+
+typedef struct {
+    int64_t cells_integrated; /* cells that ran the Rosenbrock solver */
+    int64_t cells_mapped;     /* cells that took the reference increment */
+    int64_t cells_failed;     /* status not OK/MAPPED */
+    int64_t steps_accepted;
+    int64_t steps_rejected;
+    int32_t max_cell_steps;   /* largest accepted+rejected count of any cell */
+    int32_t reserved;
+    double ms_total;          /* wall time of the call's GPU work (events) */
+} chem_stats;
+
+/* Create a context on HIP device `hip_device`, enqueueing on `hip_stream`
+ * (a hipStream_t; NULL = the device's null stream).  *out receives the
+ * context, owned by the caller until chem_destroy. */
+int chem_create(chem_ctx **out, int hip_device, void *hip_stream);
+void chem_destroy(chem_ctx *ctx);
+int chem_set_stream(chem_ctx *ctx, void *hip_stream);
+const char *chem_last_error(const chem_ctx *ctx);
+
+/* Validate and upload a mechanism (the per-cell reactor the paper leaves to
+ * the standard chemistry model, program summary and Sec. 2.1).  Rejects:
+ * N < 1 or N > 160, R < 1 or R > 4096, element-unbalanced reactions (integer
+ * check), W inconsistent with the composition, cp <= 0 anywhere on
+ * [200, 10000] K, A <= 0, indices out of range, efficiencies on
+ * non-third-body reactions (CHEM_E_BAD_MECHANISM).  Synchronous. */
+int chem_set_mechanism(chem_ctx *ctx, const chem_mech_desc *m);
+/* largest species count the integrator handles: 63 species (64 unknowns) */
+int chem_max_species(void);
+
+int chem_set_options(chem_ctx *ctx, const chem_options *o);
+int chem_get_options(const chem_ctx *ctx, chem_options *o);
+void chem_default_options(chem_options *o);
+
+/* Preallocate workspace for up to max_cells cells so that later calls with
+ * n_cells <= max_cells allocate nothing (required before stream capture). */
+int chem_reserve(chem_ctx *ctx, int64_t max_cells);
+
+/* Reference mapping, Sec. 2.3: computes Z for every cell, picks the first cell
+ * (lowest index) with Z < Z_tol as reference and flags every later candidate
+ * that also passes the optional temperature test.
+ *   T [n] device, p [n] device (unused by the criterion, validated only),
+ *   Y [N*n] device, flags [n] device uint8 out (0 solve, 1 reference,
+ *   2 mapped), ref_index device int64 out (-1 if no candidate).
+ * n_cells = 0 is allowed (ref = -1).  Asynchronous. */
+int chem_map_reference(chem_ctx *ctx, int64_t n_cells, const double *T, const double *p,
+                       const double *Y, const chem_map_params *mp, uint8_t *flags,
+                       int64_t *ref_index);
+
+/* Advance every cell by dt: a constant-pressure adiabatic reactor in
+ * (T, Y_1..Y_N) integrated by adaptive Rodas4 with max-norm error control
+ * (the per-cell stiff ODE of Sec. 1; solution tagged with its cell, Sec. 2.2).
+ *   T [n] device in/out, p [n] device, Y [N*n] device in/out.
+ *   flags [n] device (nullable): cells flagged 2 are not integrated; they take
+ *     Y += Y_ref(after) - Y_ref(before) and T from enthalpy conservation, with
+ *     the reference cell *ref_index (device int64, required with flags).
+ *   h [n] device in/out (nullable): initial step (<= 0 means dt); on return the
+ *     step size proposed after each cell's last accepted step.
+ *   cost [n] device uint32 in/out (nullable): in, the previous call's per-cell
+ *     cost, used to order the queue heavy-first; out, attempted steps.
+ *   status [n] device uint8 out (nullable): CHEM_CELL_* per cell.
+ *   steps [2n] device int32 out (nullable): accepted (2i) and rejected (2i+1).
+ *   stats host (nullable): totals; makes the call synchronous.
+ * Returns the number of failed cells when stats is given, else 0 (or <0). */
+int chem_integrate(chem_ctx *ctx, int64_t n_cells, double *T, const double *p, double *Y,
+                   double dt, const uint8_t *flags, const int64_t *ref_index, double *h,
+                   uint32_t *cost, uint8_t *status, int32_t *steps, chem_stats *stats);
+
+/* Evaluate f(y) and the analytic Jacobian for n cells (kernel-level check of
+ * the rate and Jacobian code of the integrator).  T, p [n], Y [N*n] device;
+ * f [(N+1)*n] device out (row-major per cell: f[i*(N+1) + r]),
+ * J [(N+1)^2 * n] device out (row-major per cell), either nullable. */
+int chem_eval_rhs_jac(chem_ctx *ctx, int64_t n_cells, const double *T, const double *p,
+                      const double *Y, double *f, double *J);
+
+/* One Rodas4 step of fixed size h per cell with the analytic Jacobian
+ * (no step control): y_new and the embedded error estimate, both
+ * [(N+1)*n] device out, row-major per cell. */
+int chem_rodas_step(chem_ctx *ctx, int64_t n_cells, const double *T, const double *p,
+                    const double *Y, double h, double *ynew, double *err);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

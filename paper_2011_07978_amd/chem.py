@@ -1,0 +1,214 @@
+"""Python binding of libchem (ctypes).  Argument marshalling only.
+
+Every computation runs in the HIP kernels of libchem.so; PyTorch tensors only
+provide device memory and the HIP stream.  Names follow the C ABI in
+include/chem.h (chem_set_mechanism -> Chem.set_mechanism, ...).  There is no
+CPU fallback: without the built library or a HIP device the constructor raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libchem.so")
+
+CHEM_SCHED_PLAIN, CHEM_SCHED_QUEUE = 0, 1
+CELL_OK, CELL_MAX_STEPS, CELL_H_UNDERFLOW, CELL_NONFINITE, CELL_BAD_INPUT, CELL_MAPPED = range(6)
+
+_d = C.POINTER(C.c_double)
+_i32 = C.POINTER(C.c_int32)
+
+
+class MechDesc(C.Structure):
+    _fields_ = [("n_elements", C.c_int32), ("n_species", C.c_int32), ("n_reactions", C.c_int32),
+                ("elem_mass", _d), ("composition", _i32), ("W", _d), ("nasa", _d),
+                ("reactants", _i32), ("products", _i32), ("A", _d), ("b", _d), ("Ea", _d),
+                ("third_body", _i32), ("n_eff", C.c_int32), ("eff_reaction", _i32),
+                ("eff_species", _i32), ("eff_value", _d)]
+
+
+class Options(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("max_steps", C.c_int32),
+                ("hmin_frac", C.c_double), ("schedule", C.c_int32), ("queue_chunk", C.c_int32),
+                ("slots_per_cu", C.c_int32), ("order_by_cost", C.c_int32)]
+
+
+class MapParams(C.Structure):
+    _fields_ = [("Z_tol", C.c_double), ("T_tol", C.c_double), ("use_T", C.c_int32),
+                ("Y_fuel", _d), ("Y_ox", _d)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("cells_integrated", C.c_int64), ("cells_mapped", C.c_int64),
+                ("cells_failed", C.c_int64), ("steps_accepted", C.c_int64),
+                ("steps_rejected", C.c_int64), ("max_cell_steps", C.c_int32),
+                ("reserved", C.c_int32), ("ms_total", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+EXPORTS = ["chem_create", "chem_destroy", "chem_set_stream", "chem_last_error",
+           "chem_set_mechanism", "chem_max_species", "chem_set_options", "chem_get_options",
+           "chem_default_options", "chem_reserve", "chem_map_reference", "chem_integrate",
+           "chem_eval_rhs_jac", "chem_rodas_step"]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libchem.so and declare its signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libchem.so not built ({path}); run __graft_entry__.build()")
+    L = C.CDLL(path)
+    vp = C.c_void_p
+    L.chem_create.argtypes = [C.POINTER(vp), C.c_int, vp]
+    L.chem_destroy.argtypes = [vp]
+    L.chem_destroy.restype = None
+    L.chem_set_stream.argtypes = [vp, vp]
+    L.chem_last_error.argtypes = [vp]
+    L.chem_last_error.restype = C.c_char_p
+    L.chem_set_mechanism.argtypes = [vp, C.POINTER(MechDesc)]
+    L.chem_max_species.argtypes = []
+    L.chem_set_options.argtypes = [vp, C.POINTER(Options)]
+    L.chem_get_options.argtypes = [vp, C.POINTER(Options)]
+    L.chem_default_options.argtypes = [C.POINTER(Options)]
+    L.chem_default_options.restype = None
+    L.chem_reserve.argtypes = [vp, C.c_int64]
+    L.chem_map_reference.argtypes = [vp, C.c_int64, vp, vp, vp, C.POINTER(MapParams), vp, vp]
+    L.chem_integrate.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_double, vp, vp, vp, vp, vp, vp,
+                                 C.POINTER(Stats)]
+    L.chem_eval_rhs_jac.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp]
+    L.chem_rodas_step.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_double, vp, vp]
+    for name in EXPORTS:
+        if name not in ("chem_destroy", "chem_default_options", "chem_last_error"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return C.c_void_p(t.data_ptr())
+
+
+def _np(a, dtype):
+    import numpy as np
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+class ChemError(RuntimeError):
+    pass
+
+
+class Chem:
+    """A libchem context on one HIP device, enqueueing on torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libchem needs a HIP device; none is visible")
+        self.L = load_library()
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = C.c_void_p()
+        rc = self.L.chem_create(C.byref(h), device, C.c_void_p(self.stream.cuda_stream))
+        if rc != 0:
+            raise ChemError(f"chem_create failed ({rc})")
+        self.h = h
+        self.mech = None
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.chem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc < 0:
+            raise ChemError(f"{what} failed ({rc}): {self.L.chem_last_error(self.h).decode()}")
+        return rc
+
+    # ---------------------------------------------------------------- setup
+    def set_mechanism(self, mech):
+        import numpy as np
+        k = [_np(mech.elem_mass, np.float64), _np(mech.composition, np.int32), _np(mech.W, np.float64),
+             _np(mech.nasa, np.float64), _np(mech.reactants, np.int32), _np(mech.products, np.int32),
+             _np(mech.A, np.float64), _np(mech.b, np.float64), _np(mech.Ea, np.float64),
+             _np(mech.third_body, np.int32), _np(mech.eff_reaction, np.int32),
+             _np(mech.eff_species, np.int32), _np(mech.eff_value, np.float64)]
+        P = lambda a, t: a.ctypes.data_as(t)
+        d = MechDesc(int(mech.n_elements), int(mech.n_species), int(mech.n_reactions),
+                     P(k[0], _d), P(k[1], _i32), P(k[2], _d), P(k[3], _d), P(k[4], _i32),
+                     P(k[5], _i32), P(k[6], _d), P(k[7], _d), P(k[8], _d), P(k[9], _i32),
+                     int(k[12].size), P(k[10], _i32), P(k[11], _i32), P(k[12], _d))
+        self._check(self.L.chem_set_mechanism(self.h, C.byref(d)), "chem_set_mechanism")
+        self.mech = mech
+        return self
+
+    def options(self) -> Options:
+        o = Options()
+        self._check(self.L.chem_get_options(self.h, C.byref(o)), "chem_get_options")
+        return o
+
+    def set_options(self, **kw):
+        o = self.options()
+        for key, v in kw.items():
+            setattr(o, key, v)
+        self._check(self.L.chem_set_options(self.h, C.byref(o)), "chem_set_options")
+        return o
+
+    def reserve(self, max_cells: int):
+        self._check(self.L.chem_reserve(self.h, int(max_cells)), "chem_reserve")
+
+    # ------------------------------------------------------------ hot path
+    def map_reference(self, T, p, Y, Y_fuel, Y_ox, Z_tol, T_tol=1.0, use_T=False,
+                      flags=None, ref_index=None):
+        import numpy as np
+        n = T.shape[0]
+        if flags is None:
+            flags = torch.empty(n, dtype=torch.uint8, device=T.device)
+        if ref_index is None:
+            ref_index = torch.empty(1, dtype=torch.int64, device=T.device)
+        yf, yo = _np(Y_fuel, np.float64), _np(Y_ox, np.float64)
+        mp = MapParams(float(Z_tol), float(T_tol), 1 if use_T else 0,
+                       yf.ctypes.data_as(_d), yo.ctypes.data_as(_d))
+        self._check(self.L.chem_map_reference(self.h, n, _ptr(T), _ptr(p), _ptr(Y), C.byref(mp),
+                                              _ptr(flags), _ptr(ref_index)), "chem_map_reference")
+        return flags, ref_index
+
+    def integrate(self, T, p, Y, dt, flags=None, ref_index=None, h=None, cost=None,
+                  status=None, steps=None, stats=False):
+        n = T.shape[0]
+        st = Stats() if stats else None
+        rc = self.L.chem_integrate(self.h, n, _ptr(T), _ptr(p), _ptr(Y), float(dt), _ptr(flags),
+                                   _ptr(ref_index), _ptr(h), _ptr(cost), _ptr(status),
+                                   _ptr(steps), C.byref(st) if st is not None else None)
+        self._check(rc, "chem_integrate")
+        return st.as_dict() if st is not None else None
+
+    def eval_rhs_jac(self, T, p, Y, f=None, J=None):
+        self._check(self.L.chem_eval_rhs_jac(self.h, T.shape[0], _ptr(T), _ptr(p), _ptr(Y),
+                                             _ptr(f), _ptr(J)), "chem_eval_rhs_jac")
+        return f, J
+
+    def rodas_step(self, T, p, Y, h, ynew, err):
+        self._check(self.L.chem_rodas_step(self.h, T.shape[0], _ptr(T), _ptr(p), _ptr(Y), float(h),
+                                           _ptr(ynew), _ptr(err)), "chem_rodas_step")
+        return ynew, err

@@ -1,0 +1,567 @@
+// C-ABI of libchem: validation, mechanism packing, workspace and dispatch.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/chem.h"
+#include "mech_dev.hpp"
+
+namespace chem {
+int pick_np(int n);
+hipError_t launch_integrate(int NP, const MechDev &M, const MechDev *Md, const IntParams &P,
+                            int schedule, int grid, hipStream_t s);
+int queue_occupancy(int NP, const MechDev &M);
+hipError_t launch_eval_rhs_jac(int NP, const MechDev &M, const MechDev *Md, const IntParams &P,
+                               double *f, double *J, hipStream_t s);
+hipError_t launch_rodas_step(int NP, const MechDev &M, const MechDev *Md, const IntParams &P,
+                             double h, double *ynew, double *err, hipStream_t s);
+hipError_t launch_map(int64_t ncells, int N, const double *T, const double *Y, const double *w,
+                      double beta_f, double beta_ox, double Z_tol, double T_tol, int use_T,
+                      uint8_t *flags, unsigned long long *ref_tmp, int64_t *ref_out, hipStream_t s);
+hipError_t launch_queue_reset(int *hist, int *cursor, int *seg_ctr, int *n_active,
+                              unsigned long long *stats, hipStream_t s);
+hipError_t launch_queue_build(int64_t ncells, const uint8_t *flags, const uint32_t *cost, int *hist,
+                              int *cursor, int *n_active, int *queue, hipStream_t s);
+hipError_t launch_ref_snapshot(int64_t ncells, int N, const double *T, const double *Y,
+                               const int64_t *ref, double *snap, hipStream_t s);
+hipError_t launch_map_scatter(int64_t ncells, int N, double *T, double *Y, const uint8_t *flags,
+                              const int64_t *ref, const double *snap, double *delta,
+                              const double *nasa_t, const double *invW, uint8_t *status,
+                              unsigned long long *stats, hipStream_t s);
+}  // namespace chem
+
+using namespace chem;
+
+struct chem_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    int num_cu = 0;
+    chem_options opt;
+    // mechanism
+    bool has_mech = false;
+    int E = 0, N = 0, R = 0, NP = -1;
+    std::vector<int> comp;         // [N*E]
+    std::vector<double> elem_mass, W;
+    MechDev M{};                   // host copy (sizes, device pointers)
+    MechDev *d_mech = nullptr;     // device copy read by the kernels
+    std::vector<void *> mech_bufs;
+    // mapping weights (device) and the streams they were computed for
+    double *d_mapw = nullptr;
+    std::vector<double> map_yf, map_yo;
+    double beta_f = 0.0, beta_ox = 0.0;
+    // workspace
+    int64_t cap = 0;
+    int *d_queue = nullptr;
+    int *d_small = nullptr;        // hist[32] cursor[32] seg[8] n_active[1]
+    unsigned long long *d_stats = nullptr;   // [8]
+    unsigned long long *d_reftmp = nullptr;
+    double *d_snap = nullptr, *d_delta = nullptr;
+    unsigned long long *h_stats = nullptr;   // pinned
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    int occ = 0;
+};
+
+static int fail(chem_ctx *c, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    if (getenv("CHEM_LOG")) fprintf(stderr, "[libchem] %s\n", buf);
+    return code;
+}
+
+#define HIPCHK(c, x)                                                                 \
+    do {                                                                             \
+        hipError_t e_ = (x);                                                         \
+        if (e_ != hipSuccess)                                                        \
+            return fail(c, CHEM_E_HIP, "%s: %s", #x, hipGetErrorString(e_));         \
+    } while (0)
+
+static bool capturing(chem_ctx *c) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(c->stream, &st) != hipSuccess) return false;
+    return st != hipStreamCaptureStatusNone;
+}
+
+// Exported functions take C linkage from their declarations in chem.h.
+
+void chem_default_options(chem_options *o) {
+    o->rtol = 1e-8;
+    o->atol = 1e-12;
+    o->max_steps = 100000;
+    o->hmin_frac = 1e-14;
+    o->schedule = CHEM_SCHED_QUEUE;
+    o->queue_chunk = 0;
+    o->slots_per_cu = 0;
+    o->order_by_cost = 1;
+}
+
+int chem_max_species(void) { return 63; }
+
+int chem_create(chem_ctx **out, int hip_device, void *hip_stream) {
+    if (!out) return CHEM_E_INVALID_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev)
+        return CHEM_E_INVALID_ARG;
+    chem_ctx *c = new chem_ctx();
+    c->device = hip_device;
+    c->stream = (hipStream_t)hip_stream;
+    chem_default_options(&c->opt);
+    if (hipSetDevice(hip_device) != hipSuccess ||
+        hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, hip_device) !=
+            hipSuccess ||
+        hipHostMalloc((void **)&c->h_stats, 8 * sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc((void **)&c->d_stats, 8 * sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc((void **)&c->d_small, 80 * sizeof(int)) != hipSuccess ||
+        hipMalloc((void **)&c->d_reftmp, sizeof(unsigned long long)) != hipSuccess ||
+        hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        chem_destroy(c);
+        return CHEM_E_HIP;
+    }
+    *out = c;
+    return CHEM_OK;
+}
+
+static void free_mech(chem_ctx *c) {
+    for (void *p : c->mech_bufs) (void)hipFree(p);
+    c->mech_bufs.clear();
+    if (c->d_mapw) (void)hipFree(c->d_mapw);
+    if (c->d_snap) (void)hipFree(c->d_snap);
+    if (c->d_delta) (void)hipFree(c->d_delta);
+    c->d_mapw = c->d_snap = c->d_delta = nullptr;
+    c->d_mech = nullptr;
+    c->map_yf.clear();
+    c->map_yo.clear();
+    c->has_mech = false;
+}
+
+void chem_destroy(chem_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    free_mech(c);
+    if (c->d_queue) (void)hipFree(c->d_queue);
+    if (c->d_small) (void)hipFree(c->d_small);
+    if (c->d_stats) (void)hipFree(c->d_stats);
+    if (c->d_reftmp) (void)hipFree(c->d_reftmp);
+    if (c->h_stats) (void)hipHostFree(c->h_stats);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    delete c;
+}
+
+int chem_set_stream(chem_ctx *c, void *s) {
+    if (!c) return CHEM_E_INVALID_ARG;
+    c->stream = (hipStream_t)s;
+    return CHEM_OK;
+}
+
+const char *chem_last_error(const chem_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int chem_set_options(chem_ctx *c, const chem_options *o) {
+    if (!c || !o) return CHEM_E_INVALID_ARG;
+    if (!(o->rtol > 0.0) || !(o->atol > 0.0) || o->max_steps < 1 || !(o->hmin_frac >= 0.0) ||
+        !(o->hmin_frac < 1.0) || (o->schedule != CHEM_SCHED_PLAIN && o->schedule != CHEM_SCHED_QUEUE) ||
+        o->queue_chunk < 0 || o->queue_chunk > 4096 || o->slots_per_cu < 0 || o->slots_per_cu > 64)
+        return fail(c, CHEM_E_INVALID_ARG, "invalid options");
+    c->opt = *o;
+    return CHEM_OK;
+}
+
+int chem_get_options(const chem_ctx *c, chem_options *o) {
+    if (!c || !o) return CHEM_E_INVALID_ARG;
+    *o = c->opt;
+    return CHEM_OK;
+}
+
+template <class T>
+static int upload(chem_ctx *c, const std::vector<T> &h, const T **dptr) {
+    void *d = nullptr;
+    size_t bytes = std::max<size_t>(1, h.size()) * sizeof(T);
+    if (hipMalloc(&d, bytes) != hipSuccess) return fail(c, CHEM_E_OOM, "hipMalloc(%zu)", bytes);
+    c->mech_bufs.push_back(d);
+    if (!h.empty() && hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(c, CHEM_E_HIP, "hipMemcpy mechanism");
+    *dptr = (const T *)d;
+    return CHEM_OK;
+}
+
+int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
+    if (!c || !m) return CHEM_E_INVALID_ARG;
+    const int E = m->n_elements, N = m->n_species, R = m->n_reactions;
+    if (E < 1 || E > 16 || N < 1 || N > 160 || R < 1 || R > 4096)
+        return fail(c, CHEM_E_BAD_MECHANISM, "sizes out of range (E=%d N=%d R=%d)", E, N, R);
+    if (!m->elem_mass || !m->composition || !m->W || !m->nasa || !m->reactants || !m->products ||
+        !m->A || !m->b || !m->Ea || !m->third_body || m->n_eff < 0 ||
+        (m->n_eff > 0 && (!m->eff_reaction || !m->eff_species || !m->eff_value)))
+        return fail(c, CHEM_E_INVALID_ARG, "null mechanism array");
+    // molar masses consistent with the composition
+    for (int k = 0; k < N; ++k) {
+        double w = 0.0;
+        for (int e = 0; e < E; ++e) {
+            if (m->composition[k * E + e] < 0) return fail(c, CHEM_E_BAD_MECHANISM, "negative atom count");
+            w += m->composition[k * E + e] * m->elem_mass[e];
+        }
+        if (!(m->W[k] > 0.0) || fabs(w - m->W[k]) > 1e-9 * m->W[k])
+            return fail(c, CHEM_E_BAD_MECHANISM, "species %d: W inconsistent with composition", k);
+    }
+    // cp > 0 on [200, 10000] K
+    for (int k = 0; k < N; ++k) {
+        const double *a = m->nasa + 7 * k;
+        for (int q = 0; q <= 400; ++q) {
+            const double T = 200.0 + q * (9800.0 / 400.0);
+            const double cp = a[0] + a[1] * T + a[2] * T * T + a[3] * T * T * T + a[4] * T * T * T * T;
+            if (!(cp > 0.0)) return fail(c, CHEM_E_BAD_MECHANISM, "species %d: cp <= 0 at %g K", k, T);
+        }
+        for (int i = 0; i < 7; ++i)
+            if (!isfinite(a[i])) return fail(c, CHEM_E_BAD_MECHANISM, "species %d: non-finite thermo", k);
+    }
+    // reactions: indices, balance, parameters
+    std::vector<int> tb_slot(R, 0xffff);
+    int ntb = 0;
+    for (int j = 0; j < R; ++j) {
+        int nr = 0, np = 0;
+        std::vector<long> bal(E, 0);
+        for (int s = 0; s < 2; ++s) {
+            const int k = m->reactants[2 * j + s];
+            if (k < -1 || k >= N) return fail(c, CHEM_E_BAD_MECHANISM, "reaction %d: bad reactant", j);
+            if (k >= 0) { ++nr; for (int e = 0; e < E; ++e) bal[e] -= m->composition[k * E + e]; }
+        }
+        for (int s = 0; s < 3; ++s) {
+            const int k = m->products[3 * j + s];
+            if (k < -1 || k >= N) return fail(c, CHEM_E_BAD_MECHANISM, "reaction %d: bad product", j);
+            if (k >= 0) { ++np; for (int e = 0; e < E; ++e) bal[e] += m->composition[k * E + e]; }
+        }
+        if (nr == 0 || np == 0) return fail(c, CHEM_E_BAD_MECHANISM, "reaction %d: empty side", j);
+        for (int e = 0; e < E; ++e)
+            if (bal[e] != 0) return fail(c, CHEM_E_BAD_MECHANISM, "reaction %d: element %d unbalanced", j, e);
+        if (!(m->A[j] > 0.0) || !isfinite(m->A[j]) || !isfinite(m->b[j]) || !isfinite(m->Ea[j]))
+            return fail(c, CHEM_E_BAD_MECHANISM, "reaction %d: bad rate parameters", j);
+        if (m->third_body[j]) tb_slot[j] = ntb++;
+    }
+    std::vector<std::vector<std::pair<int, double>>> eff(ntb);
+    for (int i = 0; i < m->n_eff; ++i) {
+        const int j = m->eff_reaction[i], k = m->eff_species[i];
+        if (j < 0 || j >= R || !m->third_body[j] || k < 0 || k >= N || !(m->eff_value[i] >= 0.0) ||
+            !isfinite(m->eff_value[i]))
+            return fail(c, CHEM_E_BAD_MECHANISM, "bad third-body efficiency %d", i);
+        for (auto &pr : eff[tb_slot[j]])
+            if (pr.first == k) return fail(c, CHEM_E_BAD_MECHANISM, "duplicate efficiency %d", i);
+        eff[tb_slot[j]].push_back({k, m->eff_value[i] - 1.0});
+    }
+
+    HIPCHK(c, hipSetDevice(c->device));
+    free_mech(c);
+    c->E = E; c->N = N; c->R = R;
+    c->comp.assign(m->composition, m->composition + N * E);
+    c->elem_mass.assign(m->elem_mass, m->elem_mass + E);
+    c->W.assign(m->W, m->W + N);
+
+    // species tables
+    std::vector<double> nasa_t(14 * (size_t)N), W(N), invW(N);
+    for (int k = 0; k < N; ++k) {
+        const double *a = m->nasa + 7 * k;
+        for (int i = 0; i < 7; ++i) nasa_t[i * N + k] = a[i];
+        nasa_t[7 * N + k] = a[1] / 2.0;
+        nasa_t[8 * N + k] = a[2] / 3.0;
+        nasa_t[9 * N + k] = a[3] / 4.0;
+        nasa_t[10 * N + k] = a[4] / 5.0;
+        nasa_t[11 * N + k] = a[2] / 2.0;
+        nasa_t[12 * N + k] = a[3] / 3.0;
+        nasa_t[13 * N + k] = a[4] / 4.0;
+        W[k] = m->W[k];
+        invW[k] = 1.0 / m->W[k];
+    }
+    // species -> reactions CSR with net stoichiometric coefficients
+    std::vector<int> sp_ptr(N + 1, 0), sp_ent;
+    for (int k = 0; k < N; ++k) {
+        sp_ptr[k] = (int)sp_ent.size();
+        for (int j = 0; j < R; ++j) {
+            int nu = 0;
+            for (int s = 0; s < 2; ++s) nu -= m->reactants[2 * j + s] == k;
+            for (int s = 0; s < 3; ++s) nu += m->products[3 * j + s] == k;
+            if (nu != 0) sp_ent.push_back((j << 3) | (nu + 4));
+        }
+    }
+    sp_ptr[N] = (int)sp_ent.size();
+    // species records
+    std::vector<double> spc((size_t)N * SPC_STRIDE, 0.0);
+    for (int k = 0; k < N; ++k) {
+        double *r = &spc[(size_t)k * SPC_STRIDE];
+        for (int i = 0; i < 14; ++i) r[i] = nasa_t[i * N + k];
+        r[14] = W[k];
+        r[15] = invW[k];
+        int2 rng = make_int2(sp_ptr[k], sp_ptr[k + 1]);
+        memcpy(&r[16], &rng, sizeof rng);
+    }
+    // reactions
+    std::vector<RxnRec> rxn(R);
+    std::vector<int> tb_ptr(ntb + 1, 0), eff_sp;
+    std::vector<double> eff_am1;
+    for (int t = 0; t < ntb; ++t) {
+        tb_ptr[t] = (int)eff_sp.size();
+        for (auto &pr : eff[t]) { eff_sp.push_back(pr.first); eff_am1.push_back(pr.second); }
+    }
+    tb_ptr[ntb] = (int)eff_sp.size();
+    for (int j = 0; j < R; ++j) {
+        auto sl = [&](int k) { return k < 0 ? N : k; };
+        const int r0 = sl(m->reactants[2 * j]), r1 = sl(m->reactants[2 * j + 1]);
+        const int p0 = sl(m->products[3 * j]), p1 = sl(m->products[3 * j + 1]), p2 = sl(m->products[3 * j + 2]);
+        int snu = 0;
+        for (int s = 0; s < 2; ++s) snu -= m->reactants[2 * j + s] >= 0;
+        for (int s = 0; s < 3; ++s) snu += m->products[3 * j + s] >= 0;
+        rxn[j].idx = make_int4(r0 | (r1 << 16), p0 | (p1 << 16), p2 | (tb_slot[j] << 16), snu);
+        rxn[j].lnA = log(m->A[j]);
+        rxn[j].b = m->b[j];
+        rxn[j].EaR = m->Ea[j] / RU_J;
+        rxn[j].pad = 0.0;
+    }
+
+    MechDev &M = c->M;
+    M = MechDev{};
+    M.N = N; M.R = R; M.n = N + 1;
+    M.ldj = (M.n % 2) ? M.n : M.n + 1;
+    int rc;
+    if ((rc = upload(c, nasa_t, &M.nasa_t)) || (rc = upload(c, W, &M.W)) ||
+        (rc = upload(c, invW, &M.invW)) || (rc = upload(c, sp_ptr, &M.sp_ptr)) ||
+        (rc = upload(c, sp_ent, &M.sp_ent)) || (rc = upload(c, spc, &M.spc)) ||
+        (rc = upload(c, rxn, &M.rxn)) || (rc = upload(c, tb_ptr, &M.tb_ptr)) ||
+        (rc = upload(c, eff_sp, &M.eff_sp)) || (rc = upload(c, eff_am1, &M.eff_am1))) {
+        free_mech(c);
+        return rc;
+    }
+    // LDS layout (doubles)
+    int off = 0;
+    M.off_J = off; off += M.n * M.ldj;
+    M.off_q = off; off += R;
+    M.off_C = off; off += N + 1;
+    M.off_g = off; off += N + 1;
+    M.off_h = off; off += N + 1;
+    M.off_e = off; off += N;
+    M.off_cp = off; off += N;
+    M.off_tb = off; off += M.n;
+    M.lds_doubles = off;
+    {
+        std::vector<MechDev> one(1, M);
+        const MechDev *dm = nullptr;
+        if ((rc = upload(c, one, &dm))) { free_mech(c); return rc; }
+        c->d_mech = const_cast<MechDev *>(dm);
+    }
+
+    if (hipMalloc((void **)&c->d_mapw, sizeof(double) * N) != hipSuccess ||
+        hipMalloc((void **)&c->d_snap, sizeof(double) * (N + 1)) != hipSuccess ||
+        hipMalloc((void **)&c->d_delta, sizeof(double) * N) != hipSuccess) {
+        free_mech(c);
+        return fail(c, CHEM_E_OOM, "hipMalloc mapping buffers");
+    }
+    c->NP = pick_np(M.n);
+    c->occ = 0;
+    if (c->NP > 0 && (size_t)M.lds_doubles * 8 <= 160 * 1024) c->occ = queue_occupancy(c->NP, M);
+    c->has_mech = true;
+    return CHEM_OK;
+}
+
+int chem_reserve(chem_ctx *c, int64_t max_cells) {
+    if (!c || max_cells < 0 || max_cells > (int64_t)INT32_MAX) return CHEM_E_INVALID_ARG;
+    if (max_cells <= c->cap) return CHEM_OK;
+    if (capturing(c)) return fail(c, CHEM_E_CAPTURE_UNSAFE, "workspace growth during capture");
+    HIPCHK(c, hipSetDevice(c->device));
+    if (c->d_queue) {
+        HIPCHK(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize());
+        (void)hipFree(c->d_queue);
+        c->d_queue = nullptr;
+        c->cap = 0;
+    }
+    if (hipMalloc((void **)&c->d_queue, sizeof(int) * (size_t)std::max<int64_t>(1, max_cells)) != hipSuccess)
+        return fail(c, CHEM_E_OOM, "hipMalloc queue (%lld cells)", (long long)max_cells);
+    c->cap = max_cells;
+    return CHEM_OK;
+}
+
+// Mixture-fraction weights, evaluated with separately rounded operations in a
+// fixed order (see chem_map_params).
+#pragma clang fp contract(off)
+static void map_weights(const chem_ctx *c, const double *Yf, const double *Yo, double *w,
+                        double *bf, double *bo) {
+    const int E = c->E, N = c->N;
+    std::vector<double> ce(E);
+    for (int e = 0; e < E; ++e) {
+        double zf = 0.0, zo = 0.0;
+        for (int k = 0; k < N; ++k) {
+            double t = (double)c->comp[k * E + e] * c->elem_mass[e];
+            double tf = t * Yf[k];
+            tf = tf / c->W[k];
+            zf = zf + tf;
+            double to = t * Yo[k];
+            to = to / c->W[k];
+            zo = zo + to;
+        }
+        ce[e] = (zf - zo) / c->elem_mass[e];
+    }
+    for (int k = 0; k < N; ++k) {
+        double acc = 0.0;
+        for (int e = 0; e < E; ++e) {
+            double t = ce[e] * (double)c->comp[k * E + e];
+            t = t * c->elem_mass[e];
+            t = t / c->W[k];
+            acc = acc + t;
+        }
+        w[k] = acc;
+    }
+    double sf = 0.0, so = 0.0;
+    for (int k = 0; k < N; ++k) {
+        double t = w[k] * Yf[k];
+        sf = sf + t;
+        t = w[k] * Yo[k];
+        so = so + t;
+    }
+    *bf = sf;
+    *bo = so;
+}
+#pragma clang fp contract(on)
+
+int chem_map_reference(chem_ctx *c, int64_t n, const double *T, const double *p, const double *Y,
+                       const chem_map_params *mp, uint8_t *flags, int64_t *ref_index) {
+    if (!c || !mp || !ref_index || n < 0 || !mp->Y_fuel || !mp->Y_ox || !(mp->Z_tol == mp->Z_tol) ||
+        (mp->use_T && !(mp->T_tol >= 0.0)))
+        return fail(c, CHEM_E_INVALID_ARG, "chem_map_reference: bad arguments");
+    if (n > 0 && (!T || !p || !Y || !flags)) return fail(c, CHEM_E_INVALID_ARG, "null array");
+    if (!c->has_mech) return fail(c, CHEM_E_NO_MECHANISM, "no mechanism");
+    HIPCHK(c, hipSetDevice(c->device));
+    const int N = c->N;
+    const bool same = c->map_yf.size() == (size_t)N &&
+                      std::equal(c->map_yf.begin(), c->map_yf.end(), mp->Y_fuel) &&
+                      std::equal(c->map_yo.begin(), c->map_yo.end(), mp->Y_ox);
+    if (!same) {
+        if (capturing(c)) return fail(c, CHEM_E_CAPTURE_UNSAFE, "new mapping streams during capture");
+        std::vector<double> w(N);
+        map_weights(c, mp->Y_fuel, mp->Y_ox, w.data(), &c->beta_f, &c->beta_ox);
+        if (!(c->beta_f != c->beta_ox)) return fail(c, CHEM_E_INVALID_ARG, "fuel and oxidiser streams coincide");
+        HIPCHK(c, hipMemcpy(c->d_mapw, w.data(), sizeof(double) * N, hipMemcpyHostToDevice));
+        c->map_yf.assign(mp->Y_fuel, mp->Y_fuel + N);
+        c->map_yo.assign(mp->Y_ox, mp->Y_ox + N);
+    }
+    HIPCHK(c, launch_map(n, N, T, Y, c->d_mapw, c->beta_f, c->beta_ox, mp->Z_tol, mp->T_tol,
+                         mp->use_T ? 1 : 0, flags, c->d_reftmp, ref_index, c->stream));
+    return CHEM_OK;
+}
+
+static int check_integrator(chem_ctx *c) {
+    if (!c->has_mech) return fail(c, CHEM_E_NO_MECHANISM, "no mechanism");
+    if (c->NP < 0)
+        return fail(c, CHEM_E_UNIMPL, "mechanisms with more than %d species are not supported by "
+                                      "the register-resident integrator", chem_max_species());
+    if ((size_t)c->M.lds_doubles * 8 > 160 * 1024)
+        return fail(c, CHEM_E_UNIMPL, "mechanism tables exceed LDS (%d bytes)", c->M.lds_doubles * 8);
+    return CHEM_OK;
+}
+
+int chem_integrate(chem_ctx *c, int64_t n, double *T, const double *p, double *Y, double dt,
+                   const uint8_t *flags, const int64_t *ref_index, double *h, uint32_t *cost,
+                   uint8_t *status, int32_t *steps, chem_stats *stats) {
+    if (!c) return CHEM_E_INVALID_ARG;
+    if (n < 0 || n > (int64_t)INT32_MAX || !(dt > 0.0) || !isfinite(dt))
+        return fail(c, CHEM_E_INVALID_ARG, "chem_integrate: bad n or dt");
+    if (n > 0 && (!T || !p || !Y)) return fail(c, CHEM_E_INVALID_ARG, "null state array");
+    if (flags && !ref_index) return fail(c, CHEM_E_INVALID_ARG, "flags need ref_index");
+    int rc = check_integrator(c);
+    if (rc) return rc;
+    HIPCHK(c, hipSetDevice(c->device));
+    const bool cap = capturing(c);
+    if (stats && cap) return fail(c, CHEM_E_CAPTURE_UNSAFE, "stats requested during capture");
+    if (c->opt.schedule == CHEM_SCHED_QUEUE && n > c->cap) {
+        if ((rc = chem_reserve(c, n))) return rc;
+    }
+    hipStream_t s = c->stream;
+    if (stats) HIPCHK(c, hipEventRecord(c->ev0, s));
+    int *hist = c->d_small, *cursor = c->d_small + 32, *seg = c->d_small + 64, *nact = c->d_small + 72;
+    HIPCHK(c, launch_queue_reset(hist, cursor, seg, nact, c->d_stats, s));
+    if (n > 0) {
+        if (flags) HIPCHK(c, launch_ref_snapshot(n, c->N, T, Y, ref_index, c->d_snap, s));
+        IntParams P{};
+        P.rtol = c->opt.rtol;
+        P.atol = c->opt.atol;
+        P.hmin_frac = c->opt.hmin_frac;
+        P.dt = dt;
+        P.max_steps = c->opt.max_steps;
+        P.ncells = n;
+        P.T = T; P.p = p; P.Y = Y; P.h = h; P.cost = cost; P.status = status; P.steps = steps;
+        P.flags = flags;
+        P.stats = c->d_stats;
+        int grid = 0;
+        if (c->opt.schedule == CHEM_SCHED_QUEUE) {
+            HIPCHK(c, launch_queue_build(n, flags, c->opt.order_by_cost ? cost : nullptr, hist, cursor,
+                                         nact, c->d_queue, s));
+            P.queue = c->d_queue;
+            P.seg_ctr = seg;
+            P.n_active = nact;
+            P.chunk = c->opt.queue_chunk > 0 ? c->opt.queue_chunk : 1;
+            const int slots = c->opt.slots_per_cu > 0 ? c->opt.slots_per_cu : std::max(1, c->occ);
+            grid = c->num_cu * slots;
+            if (grid > n) grid = (int)n;
+        }
+        HIPCHK(c, launch_integrate(c->NP, c->M, c->d_mech, P, c->opt.schedule, grid, s));
+        if (flags)
+            HIPCHK(c, launch_map_scatter(n, c->N, T, Y, flags, ref_index, c->d_snap, c->d_delta,
+                                         c->M.nasa_t, c->M.invW, status, c->d_stats, s));
+    }
+    if (!stats) return CHEM_OK;
+    HIPCHK(c, hipEventRecord(c->ev1, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_stats, c->d_stats, 8 * sizeof(unsigned long long),
+                             hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    float ms = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    stats->cells_integrated = (int64_t)c->h_stats[0];
+    stats->steps_accepted = (int64_t)c->h_stats[1];
+    stats->steps_rejected = (int64_t)c->h_stats[2];
+    stats->cells_failed = (int64_t)c->h_stats[3];
+    stats->max_cell_steps = (int32_t)c->h_stats[4];
+    stats->cells_mapped = (int64_t)c->h_stats[5];
+    stats->reserved = 0;
+    stats->ms_total = ms;
+    return (int)std::min<int64_t>(stats->cells_failed, INT32_MAX);
+}
+
+int chem_eval_rhs_jac(chem_ctx *c, int64_t n, const double *T, const double *p, const double *Y,
+                      double *f, double *J) {
+    if (!c || n < 0 || n > (int64_t)INT32_MAX || (n > 0 && (!T || !p || !Y)))
+        return fail(c, CHEM_E_INVALID_ARG, "chem_eval_rhs_jac: bad arguments");
+    int rc = check_integrator(c);
+    if (rc) return rc;
+    if (n == 0) return CHEM_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    IntParams P{};
+    P.ncells = n;
+    P.T = const_cast<double *>(T); P.p = p; P.Y = const_cast<double *>(Y);
+    HIPCHK(c, launch_eval_rhs_jac(c->NP, c->M, c->d_mech, P, f, J, c->stream));
+    return CHEM_OK;
+}
+
+int chem_rodas_step(chem_ctx *c, int64_t n, const double *T, const double *p, const double *Y,
+                    double h, double *ynew, double *err) {
+    if (!c || n < 0 || n > (int64_t)INT32_MAX || !(h > 0.0) || (n > 0 && (!T || !p || !Y || !ynew || !err)))
+        return fail(c, CHEM_E_INVALID_ARG, "chem_rodas_step: bad arguments");
+    int rc = check_integrator(c);
+    if (rc) return rc;
+    if (n == 0) return CHEM_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    IntParams P{};
+    P.ncells = n;
+    P.T = const_cast<double *>(T); P.p = p; P.Y = const_cast<double *>(Y);
+    HIPCHK(c, launch_rodas_step(c->NP, c->M, c->d_mech, P, h, ynew, err, c->stream));
+    return CHEM_OK;
+}
+

@@ -1,0 +1,614 @@
+// Per-cell stiff chemistry integration on CDNA4 (gfx950), FP64.
+//
+// One 64-lane wavefront owns one cell.  Lane r holds unknown r of the state
+// y = (T, Y_1..Y_N), so species k lives on lane k + 1.  The right-hand side
+// (mass-action kinetics with reverse rates from equilibrium constants of the
+// NASA-7 thermo, third-body enhancement), the analytic Jacobian and the Rodas4
+// stages are evaluated cooperatively:
+//   - reaction pass, lane = reaction (stride 64): rate constants, rates of
+//     progress, and for the Jacobian the per-slot derivatives, scattered into
+//     an LDS Jacobian with LDS float atomics;
+//   - species pass, lane = species: production rates gathered through a
+//     species -> reaction CSR in fixed order;
+//   - LU with partial pivoting, row-per-lane in registers: lane r holds row r
+//     of M = I/(gamma h) - J; the pivot row is broadcast with readlane and no
+//     row is moved, each lane only remembers at which step it became pivot;
+//   - triangular solves follow the same layout.
+// The cell's arithmetic does not depend on which workgroup runs it, so the
+// static launch and the work-queue launch give bit-identical results.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include "mech_dev.hpp"
+#include "wave.hpp"
+
+namespace chem {
+
+// Rodas4, Hairer & Wanner, Solving ODEs II, Sec. IV.7, transformed form:
+// (I/(gamma h) - J) u_i = f(y + sum_j a_ij u_j) + sum_j (c_ij / h) u_j.
+// Row 5 of A is the stage-6 input (a_5j, then 1 for u_5).
+__constant__ double kRodasA[6][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.544, 0, 0, 0, 0, 0},
+    {0.9466785280815826, 0.2557011698983284, 0, 0, 0, 0},
+    {3.314825187068521, 2.896124015972201, 0.9986419139977817, 0, 0, 0},
+    {1.221224509226641, 6.019134481288629, 12.53708332932087, -0.6878860361058950, 0, 0},
+    {1.221224509226641, 6.019134481288629, 12.53708332932087, -0.6878860361058950, 1.0, 0}};
+__constant__ double kRodasC[6][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {-5.6688, 0, 0, 0, 0, 0},
+    {-2.430093356833875, -0.2063599157091915, 0, 0, 0, 0},
+    {-0.1073529058151375, -9.594562251023355, -20.47028614809616, 0, 0, 0},
+    {7.496443313967647, -10.24680431464352, -33.99990352819905, 11.70890893206160, 0, 0},
+    {8.083246795921522, -7.981132988064893, -31.52159432874371, 16.31930543123136,
+     -6.058818238834054, 0}};
+constexpr double kGamma = 0.25;
+
+__device__ __forceinline__ void lds_add(double *p, double v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// -----------------------------------------------------------------------------
+// f(y), and with JAC the analytic Jacobian into LDS (row-major, stride ldj).
+// Returns f_r on lane r.  All lanes of the wave must call it.
+// -----------------------------------------------------------------------------
+template <bool JAC>
+__device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const double p,
+                                           const double y, double *__restrict__ lds) {
+    // The memory clobber keeps the descriptor loads, and the opaque lane index
+    // every per-lane address, local to this call instead of being hoisted out
+    // of the step loop and held in registers across it.
+    asm volatile("" ::: "memory");
+    int lane = lane_id();
+    asm volatile("" : "+v"(lane));
+    const MechDev &M = *Mp;
+    const int N = M.N, R = M.R, n = M.n, ldj = M.ldj;
+    double *__restrict__ Jl = lds + M.off_J;
+    double *__restrict__ ql = lds + M.off_q;
+    double *__restrict__ Cl = lds + M.off_C;
+    double *__restrict__ gl = lds + M.off_g;
+    double *__restrict__ hl = lds + M.off_h;
+    double *__restrict__ el = lds + M.off_e;
+    double *__restrict__ cpl = lds + M.off_cp;
+    double *__restrict__ tbl = lds + M.off_tb;
+
+    const double T = readlane_d(y, 0);
+    const double lnT = log(T);
+    const double invT = 1.0 / T;
+    const bool sp = lane >= 1 && lane <= N;
+    const int k = sp ? lane - 1 : 0;
+
+    // species thermo (NASA-7 single range), Horner form
+    double cpR = 0.0, hRT = 0.0, gRT = 0.0, dcpR = 0.0, invWk = 0.0, Wk = 0.0;
+    int csr0 = 0, csr1 = 0;
+    if (sp) {
+        const double *a = M.spc + k * SPC_STRIDE;
+        const double a1 = a[0], a2 = a[1], a3 = a[2], a4 = a[3], a5 = a[4], a6 = a[5], a7 = a[6];
+        const double h2 = a[7], h3 = a[8], h4 = a[9], h5 = a[10];
+        const double s3 = a[11], s4 = a[12], s5 = a[13];
+        cpR = a1 + T * (a2 + T * (a3 + T * (a4 + T * a5)));
+        hRT = a1 + T * (h2 + T * (h3 + T * (h4 + T * h5))) + a6 * invT;
+        const double sR = a1 * lnT + T * (a2 + T * (s3 + T * (s4 + T * s5))) + a7;
+        gRT = hRT - sR;
+        if (JAC) dcpR = a2 + T * (2.0 * a3 + T * (3.0 * a4 + T * (4.0 * a5)));
+        Wk = a[14];
+        invWk = a[15];
+        const int2 rng = *reinterpret_cast<const int2 *>(a + 16);
+        csr0 = rng.x;
+        csr1 = rng.y;
+    }
+    const double yw = sp ? y * invWk : 0.0;
+    const double sumYW = wave_sum(yw);
+    const double rho = p / (RU_ERG * T * sumYW);
+    const double Ctot = rho * sumYW;
+    if (sp) {
+        Cl[k] = rho * yw;
+        gl[k] = gRT;
+        if (JAC) {
+            hl[k] = hRT;
+            el[k] = hRT * invWk;
+            cpl[k] = cpR * invWk;
+        }
+    }
+    if (JAC) {
+        for (int i = lane; i < n * ldj; i += 64) Jl[i] = 0.0;
+        if (lane < n) tbl[lane] = 0.0;
+    }
+    __syncthreads();
+
+    // reaction pass
+    const double ln_patm_RT = log(P_ATM / (RU_ERG * T));
+#pragma unroll 1
+    for (int j = lane; j < R; j += 64) {
+        const RxnRec &rec = M.rxn[j];
+        const int4 ix = rec.idx;
+        const int r0 = ix.x & 0xffff, r1 = (int)((unsigned)ix.x >> 16);
+        const int p0 = ix.y & 0xffff, p1 = (int)((unsigned)ix.y >> 16);
+        const int p2 = ix.z & 0xffff, tb = (int)((unsigned)ix.z >> 16);
+        const double Cr0 = Cl[r0], Cr1 = Cl[r1], Cp0 = Cl[p0], Cp1 = Cl[p1], Cp2 = Cl[p2];
+        const double dG = -gl[r0] - gl[r1] + gl[p0] + gl[p1] + gl[p2];
+        const double bj = rec.b, EaRj = rec.EaR;
+        const double ln_kf = rec.lnA + bj * lnT - EaRj * invT;
+        const double ln_Kc = -dG + (double)ix.w * ln_patm_RT;
+        const double kf = exp(ln_kf);
+        const double kr = exp(ln_kf - ln_Kc);
+        const double Pf = Cr0 * Cr1;
+        const double Pr = Cp0 * Cp1 * Cp2;
+        const bool tbr = tb != 0xffff;
+        double m = 1.0;
+        int e0 = 0, e1 = 0;
+        if (tbr) {
+            e0 = M.tb_ptr[tb];
+            e1 = M.tb_ptr[tb + 1];
+            m = Ctot;
+            for (int e = e0; e < e1; ++e) m += M.eff_am1[e] * Cl[M.eff_sp[e]];
+        }
+        const double Delta = kf * Pf - kr * Pr;
+        ql[j] = m * Delta;
+        if (JAC) {
+            const double dlnkf = bj * invT + EaRj * invT * invT;
+            const double dH = -hl[r0] - hl[r1] + hl[p0] + hl[p1] + hl[p2];
+            const double dlnkr = dlnkf - (dH - (double)ix.w) * invT;
+            const double mkf = m * kf, mkr = m * kr;
+            const double dqdT = mkf * dlnkf * Pf - mkr * dlnkr * Pr;
+            const int sl[5] = {r0, r1, p0, p1, p2};
+            const double ds[5] = {mkf * Cr1, mkf * Cr0, -mkr * Cp1 * Cp2, -mkr * Cp0 * Cp2,
+                                  -mkr * Cp0 * Cp1};
+#pragma unroll
+            for (int a = 0; a < 5; ++a) {
+                const int sa = sl[a];
+                if (sa >= N) continue;
+                const double nu = a < 2 ? -1.0 : 1.0;
+                double *row = Jl + (sa + 1) * ldj;
+                lds_add(row, nu * dqdT);
+#pragma unroll
+                for (int b = 0; b < 5; ++b)
+                    if (sl[b] < N) lds_add(row + 1 + sl[b], nu * ds[b]);
+                if (tbr) {
+                    lds_add(tbl + sa + 1, nu * Delta);
+                    for (int e = e0; e < e1; ++e)
+                        lds_add(row + 1 + M.eff_sp[e], nu * M.eff_am1[e] * Delta);
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // species pass: omega_k by the species -> reaction CSR, in reaction order
+    double fk = 0.0;
+    if (sp) {
+        double om = 0.0;
+        for (int e = csr0; e < csr1; ++e) {
+            const int ent = M.sp_ent[e];
+            om += (double)((ent & 7) - 4) * ql[ent >> 3];
+        }
+        fk = Wk * om / rho;
+    }
+    const double hs = wave_sum(sp ? hRT * invWk * fk : 0.0);
+    const double cps = wave_sum(sp ? y * cpR * invWk : 0.0);
+    const double fT = -T * hs / cps;
+
+    if (JAC) {
+        const double cpf = wave_sum(sp ? cpR * invWk * fk : 0.0);
+        const double dcps = wave_sum(sp ? y * dcpR * invWk : 0.0);
+        const double Wbar = 1.0 / sumYW;
+        // species rows: chain rule from concentrations to (T, Y)
+        if (sp) {
+            double *row = Jl + lane * ldj;
+            const double tbk = tbl[lane];
+            double s = 0.0;
+            for (int l = 0; l < N; ++l) s += (row[1 + l] + tbk) * Cl[l];
+            const double cst = fk * Wbar - Wk * Wbar * s / rho;
+            for (int i = 0; i < N; ++i) row[1 + i] = M.invW[i] * (Wk * (row[1 + i] + tbk) + cst);
+            row[0] = Wk / rho * (row[0] - s * invT) + fk * invT;
+        }
+        __syncthreads();
+        // temperature row: J_T,c = -(sum_k e_k J_kc)/cp - f_T dcp/dy_c / cp
+        if (lane < n) {
+            double acc = 0.0;
+            for (int kk = 0; kk < N; ++kk) acc += el[kk] * Jl[(kk + 1) * ldj + lane];
+            acc *= T;
+            double v;
+            if (lane == 0) v = -(cpf + acc) / cps - fT * dcps / cps;
+            else v = -acc / cps - fT * cpl[lane - 1] / cps;
+            Jl[lane] = v;
+        }
+        __syncthreads();
+    }
+    return lane == 0 ? fT : fk;
+}
+
+// -----------------------------------------------------------------------------
+// LU with partial pivoting, row-per-lane.  On return lane r holds its row of
+// L (columns before its pivot step t) and U (columns from t on); dinv = 1/U_tt;
+// lane k holds pk = the lane that became pivot at step k.
+// -----------------------------------------------------------------------------
+template <int NP>
+__device__ __forceinline__ bool lu_factor(double (&a)[NP], int &t, double &dinv, int &pk) {
+    int lane = lane_id();
+    asm volatile("" : "+v"(lane));
+    const bool active = lane < NP;
+    t = -1;
+    dinv = 0.0;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const bool cand = active && t < 0;
+        const double v = cand ? fabs(a[k]) : -1.0;
+        const double vmax = wave_max(v);
+        const unsigned long long bal = __ballot(cand && v == vmax);
+        // no candidate (NaN column): fall back to lane 0; detected below
+        const int p = bal ? (int)__builtin_ctzll(bal) : 0;
+        const double piv = readlane_d(a[k], p);
+        const double rinv = 1.0 / piv;
+        if (lane == p) {
+            t = k;
+            dinv = rinv;
+        }
+        const bool upd = active && t < 0;
+        const double l = upd ? a[k] * rinv : 0.0;
+        if (upd) a[k] = l;
+#pragma unroll
+        for (int j = k + 1; j < NP; ++j) {
+            const double pj = readlane_d(a[j], p);
+            a[j] = fma(-l, pj, a[j]);
+            // bound how many broadcast values the scheduler keeps in flight
+            if (((j - k) & 7) == 0) __builtin_amdgcn_sched_barrier(0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    // singular (zero pivot -> infinite reciprocal), NaN pivots, or a lane
+    // chosen twice (some row never became pivot)
+    const bool bad = active && (t < 0 || !(fabs(dinv) < INFINITY));
+    const int dst = active && t >= 0 ? t : lane;
+    pk = __builtin_amdgcn_ds_permute(dst << 2, lane);
+    return !wave_any(bad);
+}
+
+template <int NP>
+__device__ __forceinline__ double lu_solve(const double (&a)[NP], int t, const double dinv,
+                                           int pk, double b) {
+    // keep the pivot lookups and masks inside this call (not hoisted across
+    // calls, where they would hold ~3 NP scalar register pairs)
+    asm volatile("" : "+v"(pk), "+v"(t));
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int p = __builtin_amdgcn_readlane(pk, k);
+        const double yk = readlane_d(b, p);
+        if (t > k) b = fma(-a[k], yk, b);
+        if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int k = NP - 1; k >= 0; --k) {
+        const int p = __builtin_amdgcn_readlane(pk, k);
+        const double xk = readlane_d(b * dinv, p);
+        if (t < k) b = fma(-a[k], xk, b);
+        if (t == k) b = xk;
+        if ((k & 7) == 0) __builtin_amdgcn_sched_barrier(0);
+    }
+    return shfl_d(b, pk);
+}
+
+template <int NP>
+__device__ __forceinline__ void build_matrix(const MechDev *__restrict__ Mp,
+                                             const double *__restrict__ lds, double diag,
+                                             double (&a)[NP]) {
+    asm volatile("" ::: "memory");
+    const MechDev &M = *Mp;
+    int lane = lane_id();
+    asm volatile("" : "+v"(lane));
+    const int n = M.n;
+    const bool row_ok = lane < n;
+    const double *Jl = lds + M.off_J + (row_ok ? lane : 0) * M.ldj;
+#pragma unroll
+    for (int c = 0; c < NP; ++c) {
+        const double x = Jl[c < n ? c : 0];
+        double v = (row_ok && c < n) ? -x : 0.0;
+        if (c == lane) v += row_ok ? diag : 1.0;
+        a[c] = v;
+    }
+}
+
+// One Rodas4 attempt of size h from y (f0 = f(y), J in LDS).  Returns false
+// when M is singular.  ynew and err are per lane.
+template <int NP>
+__device__ __forceinline__ bool rodas_attempt(const MechDev *__restrict__ M, double p, double y,
+                                              double f0, double h, double *lds, double &ynew,
+                                              double &err) {
+    double a[NP];
+    build_matrix<NP>(M, lds, 1.0 / (kGamma * h), a);
+    int t, pk;
+    double dinv;
+    const bool ok = lu_factor<NP>(a, t, dinv, pk);
+    if (!ok) return false;
+    double u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0, u4 = 0.0, u5 = 0.0, ys = y;
+#pragma unroll 1
+    for (int s = 0; s < 6; ++s) {
+        double rv = f0;
+        if (s > 0) {
+            ys = y;
+            ys += kRodasA[s][0] * u0;
+            ys += kRodasA[s][1] * u1;
+            ys += kRodasA[s][2] * u2;
+            ys += kRodasA[s][3] * u3;
+            ys += kRodasA[s][4] * u4;
+            rv = rhs_eval<false>(M, p, ys, lds);
+            rv += (kRodasC[s][0] / h) * u0;
+            rv += (kRodasC[s][1] / h) * u1;
+            rv += (kRodasC[s][2] / h) * u2;
+            rv += (kRodasC[s][3] / h) * u3;
+            rv += (kRodasC[s][4] / h) * u4;
+        }
+        const double us = lu_solve<NP>(a, t, dinv, pk, rv);
+        u0 = s == 0 ? us : u0;
+        u1 = s == 1 ? us : u1;
+        u2 = s == 2 ? us : u2;
+        u3 = s == 3 ? us : u3;
+        u4 = s == 4 ? us : u4;
+        u5 = s == 5 ? us : u5;
+    }
+    ynew = ys + u5;
+    err = u5;
+    return true;
+}
+
+__device__ __forceinline__ void init_sentinels(const MechDev *Mp, double *lds) {
+    const MechDev &M = *Mp;
+    if (threadIdx.x == 0) {
+        lds[M.off_C + M.N] = 1.0;
+        lds[M.off_g + M.N] = 0.0;
+        lds[M.off_h + M.N] = 0.0;
+    }
+    __syncthreads();
+}
+
+// -----------------------------------------------------------------------------
+// Adaptive integration of one cell over [0, dt]
+// -----------------------------------------------------------------------------
+template <int NP>
+__device__ __forceinline__ void integrate_cell(const MechDev *__restrict__ M, const IntParams &P,
+                                               int64_t cell, double *lds) {
+    const int lane = lane_id();
+    const int n = M->n, N = M->N;
+    const double dt = P.dt;
+    const double p = P.p[cell];
+    double y = 0.0;
+    if (lane == 0) y = P.T[cell];
+    else if (lane <= N) y = P.Y[(int64_t)(lane - 1) * P.ncells + cell];
+    const double T0 = readlane_d(y, 0);
+    const bool bad_in = wave_any(lane < n && !isfinite(y)) || !(T0 > 0.0) || !(p > 0.0) ||
+                        !isfinite(p);
+    if (bad_in) {
+        if (lane == 0) {
+            if (P.status) P.status[cell] = 4;
+            if (P.steps) { P.steps[2 * cell] = 0; P.steps[2 * cell + 1] = 0; }
+            if (P.cost) P.cost[cell] = 0;
+            atomicAdd(&P.stats[0], 1ull);
+            atomicAdd(&P.stats[3], 1ull);
+        }
+        return;
+    }
+    double h = P.h ? P.h[cell] : 0.0;
+    if (!(h > 0.0)) h = dt;
+    h = uniform_d(h);
+    double hnext = h, t = 0.0;
+    int nacc = 0, nrej = 0, status = 0;
+    bool rej_last = false;
+    double f0 = rhs_eval<true>(M, p, y, lds);
+    while (t < dt) {
+        if (nacc + nrej >= P.max_steps) { status = 1; break; }
+        bool last = false;
+        if (h >= dt - t) { h = dt - t; last = true; }
+        if (h < P.hmin_frac * dt) { status = 2; break; }
+        double ynew = 0.0, ev = 0.0;
+        const bool ok = rodas_attempt<NP>(M, p, y, f0, h, lds, ynew, ev);
+        double e = 0.0;
+        bool bad = !ok;
+        if (ok) {
+            const double sc = P.atol + P.rtol * fmax(fabs(y), fabs(ynew));
+            const double r = lane < n ? fabs(ev) / sc : 0.0;
+            bad = wave_any(r != r);
+            e = uniform_d(wave_max(r));
+        }
+        if (!bad && e <= 1.0) {
+            double fac = (e == 0.0) ? 5.0 : fmin(5.0, fmax(0.2, 0.9 * pow(e, -0.25)));
+            if (rej_last) fac = fmin(fac, 1.0);
+            y = ynew;
+            t = last ? dt : t + h;
+            ++nacc;
+            hnext = uniform_d(h * fac);
+            h = hnext;
+            rej_last = false;
+            if (t < dt) f0 = rhs_eval<true>(M, p, y, lds);
+        } else {
+            const double fac = bad ? 0.2 : fmax(0.2, 0.9 * pow(e, -0.25));
+            h = uniform_d(h * fac);
+            ++nrej;
+            rej_last = true;
+        }
+    }
+    if (status == 0 && wave_any(lane < n && !isfinite(y))) status = 3;
+    if (lane == 0) P.T[cell] = y;
+    else if (lane <= N) P.Y[(int64_t)(lane - 1) * P.ncells + cell] = y;
+    if (lane == 0) {
+        if (P.h) P.h[cell] = hnext;
+        if (P.cost) P.cost[cell] = (uint32_t)(nacc + nrej);
+        if (P.status) P.status[cell] = (uint8_t)status;
+        if (P.steps) { P.steps[2 * cell] = nacc; P.steps[2 * cell + 1] = nrej; }
+        atomicAdd(&P.stats[0], 1ull);
+        atomicAdd(&P.stats[1], (unsigned long long)nacc);
+        atomicAdd(&P.stats[2], (unsigned long long)nrej);
+        if (status) atomicAdd(&P.stats[3], 1ull);
+        atomicMax(&P.stats[4], (unsigned long long)(nacc + nrej));
+    }
+}
+
+template <int NP>
+__global__ __launch_bounds__(64) void k_integrate_plain(const MechDev *__restrict__ M, IntParams P) {
+    extern __shared__ double lds[];
+    init_sentinels(M, lds);
+    const int64_t cell = blockIdx.x;
+    if (P.flags && P.flags[cell] == 2) return;
+    integrate_cell<NP>(M, P, cell, lds);
+}
+
+// Persistent workgroups draw cells from NSEG segments of the heavy-first queue
+// (segment x holds sorted positions x, x + NSEG, ...); a workgroup starts on
+// segment blockIdx % NSEG and steals from the next segments once its own is
+// drained.  Every workgroup exits after NSEG consecutive empty segments.
+template <int NP>
+__global__ __launch_bounds__(64) void k_integrate_queue(const MechDev *__restrict__ M, IntParams P) {
+    extern __shared__ double lds[];
+    init_sentinels(M, lds);
+    const int nact = uniform_i(*P.n_active);
+    const int chunk = P.chunk;
+    int seg = blockIdx.x % NSEG;
+    int probes = 0;
+    while (probes < NSEG) {
+        int c = 0;
+        if (lane_id() == 0) c = atomicAdd(&P.seg_ctr[seg], chunk);
+        c = uniform_i(__shfl(c, 0));
+        const int first = seg + NSEG * c;
+        if (first >= nact) {
+            seg = seg + 1 == NSEG ? 0 : seg + 1;
+            ++probes;
+            continue;
+        }
+        probes = 0;
+        for (int q = 0; q < chunk; ++q) {
+            const int pos = first + NSEG * q;
+            if (pos >= nact) break;
+            const int64_t cell = P.queue[pos];
+            integrate_cell<NP>(M, P, cell, lds);
+        }
+    }
+}
+
+// f(y) and J(y) per cell (kernel-level parity check of the rate/Jacobian code)
+template <int NP>
+__global__ __launch_bounds__(64) void k_eval_rhs_jac(const MechDev *__restrict__ M, IntParams P,
+                                                     double *fout, double *Jout) {
+    extern __shared__ double lds[];
+    init_sentinels(M, lds);
+    const int64_t cell = blockIdx.x;
+    const int lane = lane_id(), n = M->n, N = M->N;
+    double y = 0.0;
+    if (lane == 0) y = P.T[cell];
+    else if (lane <= N) y = P.Y[(int64_t)(lane - 1) * P.ncells + cell];
+    const double f = rhs_eval<true>(M, P.p[cell], y, lds);
+    if (fout && lane < n) fout[cell * n + lane] = f;
+    if (Jout)
+        for (int i = lane; i < n * n; i += 64)
+            Jout[cell * n * n + i] = lds[M->off_J + (i / n) * M->ldj + (i % n)];
+}
+
+template <int NP>
+__global__ __launch_bounds__(64) void k_rodas_step(const MechDev *__restrict__ M, IntParams P,
+                                                   double h, double *ynew_out, double *err_out) {
+    extern __shared__ double lds[];
+    init_sentinels(M, lds);
+    const int64_t cell = blockIdx.x;
+    const int lane = lane_id(), n = M->n, N = M->N;
+    double y = 0.0;
+    if (lane == 0) y = P.T[cell];
+    else if (lane <= N) y = P.Y[(int64_t)(lane - 1) * P.ncells + cell];
+    const double p = P.p[cell];
+    const double f0 = rhs_eval<true>(M, p, y, lds);
+    double ynew = 0.0, err = 0.0;
+    const bool ok = rodas_attempt<NP>(M, p, y, f0, h, lds, ynew, err);
+    if (!ok) { ynew = NAN; err = NAN; }
+    if (lane < n) {
+        ynew_out[cell * n + lane] = ynew;
+        err_out[cell * n + lane] = err;
+    }
+}
+
+// -----------------------------------------------------------------------------
+// host-side launchers, one instantiation per padded size
+// -----------------------------------------------------------------------------
+#define CHEM_NP_LIST(X) X(12) X(16) X(24) X(32) X(40) X(48) X(54) X(56) X(64)
+
+int pick_np(int n) {
+#define PICK(v) if (n <= v) return v;
+    CHEM_NP_LIST(PICK)
+#undef PICK
+    return -1;
+}
+
+static size_t lds_bytes(const MechDev &M) { return sizeof(double) * (size_t)M.lds_doubles; }
+
+// Host launchers: M is the host copy (sizes), Md the device copy the kernels read.
+
+template <int NP>
+static hipError_t launch_integrate_np(const MechDev &M, const MechDev *Md, const IntParams &P,
+                                      int schedule, int grid, hipStream_t s) {
+    const size_t sh = lds_bytes(M);
+    if (schedule == 0) {
+        hipFuncSetAttribute((const void *)k_integrate_plain<NP>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+        hipLaunchKernelGGL(k_integrate_plain<NP>, dim3((unsigned)P.ncells), dim3(64), sh, s, Md, P);
+    } else {
+        hipFuncSetAttribute((const void *)k_integrate_queue<NP>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+        hipLaunchKernelGGL(k_integrate_queue<NP>, dim3((unsigned)grid), dim3(64), sh, s, Md, P);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_integrate(int NP, const MechDev &M, const MechDev *Md, const IntParams &P,
+                            int schedule, int grid, hipStream_t s) {
+    switch (NP) {
+#define CASE(v) case v: return launch_integrate_np<v>(M, Md, P, schedule, grid, s);
+        CHEM_NP_LIST(CASE)
+#undef CASE
+    }
+    return hipErrorInvalidValue;
+}
+
+int queue_occupancy(int NP, const MechDev &M) {
+    int blocks = 0;
+    const size_t sh = lds_bytes(M);
+    switch (NP) {
+#define CASE(v)                                                                                 \
+    case v:                                                                                     \
+        hipFuncSetAttribute((const void *)k_integrate_queue<v>,                                 \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);               \
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_integrate_queue<v>, 64, sh);    \
+        break;
+        CHEM_NP_LIST(CASE)
+#undef CASE
+    }
+    return blocks;
+}
+
+hipError_t launch_eval_rhs_jac(int NP, const MechDev &M, const MechDev *Md, const IntParams &P,
+                               double *f, double *J, hipStream_t s) {
+    const size_t sh = lds_bytes(M);
+    switch (NP) {
+#define CASE(v)                                                                                 \
+    case v:                                                                                     \
+        hipFuncSetAttribute((const void *)k_eval_rhs_jac<v>,                                    \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);               \
+        hipLaunchKernelGGL(k_eval_rhs_jac<v>, dim3((unsigned)P.ncells), dim3(64), sh, s, Md, P, f, J); \
+        return hipGetLastError();
+        CHEM_NP_LIST(CASE)
+#undef CASE
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_rodas_step(int NP, const MechDev &M, const MechDev *Md, const IntParams &P,
+                             double h, double *ynew, double *err, hipStream_t s) {
+    const size_t sh = lds_bytes(M);
+    switch (NP) {
+#define CASE(v)                                                                                 \
+    case v:                                                                                     \
+        hipFuncSetAttribute((const void *)k_rodas_step<v>,                                      \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);               \
+        hipLaunchKernelGGL(k_rodas_step<v>, dim3((unsigned)P.ncells), dim3(64), sh, s, Md, P, h, ynew, err); \
+        return hipGetLastError();
+        CHEM_NP_LIST(CASE)
+#undef CASE
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace chem

@@ -1,0 +1,67 @@
+// Wavefront-level helpers for CDNA (64-lane wavefronts, gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace chem {
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
+
+// Broadcast a double from a uniform lane index (result in scalar registers).
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// Make a value that every lane already agrees on wave-uniform (SGPR).
+__device__ __forceinline__ double uniform_d(double v) {
+    int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+    int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Lane `src` (per lane) -> value (ds_bpermute).
+__device__ __forceinline__ double shfl_d(double v, int src) {
+    int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(v));
+    int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+// DPP lane exchange inside 16-lane rows.
+//   0xB1 quad_perm [1,0,3,2] (lane ^ 1), 0x4E quad_perm [2,3,0,1] (lane ^ 2),
+//   0x141 row_half_mirror (i -> 7 - i in each 8 lanes), 0x140 row_mirror (i -> 15 - i).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Reductions over the 64 lanes.  Within each 16-lane row the two operands of
+// every combine are the same pair of values on both lanes (sum and max
+// commute), then the four row results are combined in a fixed order; every
+// lane therefore returns the same bits, independent of scheduling.
+__device__ __forceinline__ double wave_sum(double v) {
+    v += dpp_d<0xB1>(v);
+    v += dpp_d<0x4E>(v);
+    v += dpp_d<0x141>(v);
+    v += dpp_d<0x140>(v);
+    return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
+__device__ __forceinline__ double max2(double a, double b) { return a > b ? a : b; }
+
+// Maximum of values that are not NaN.
+__device__ __forceinline__ double wave_max(double v) {
+    v = max2(v, dpp_d<0xB1>(v));
+    v = max2(v, dpp_d<0x4E>(v));
+    v = max2(v, dpp_d<0x141>(v));
+    v = max2(v, dpp_d<0x140>(v));
+    return max2(max2(readlane_d(v, 0), readlane_d(v, 16)), max2(readlane_d(v, 32), readlane_d(v, 48)));
+}
+
+__device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
+
+}  // namespace chem

@@ -1,0 +1,77 @@
+"""Kernel-level parity of the HIP path with the CPU oracle: rates/RHS, the
+analytic Jacobian and one fixed-size Rodas4 step."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import Oracle  # noqa: E402
+from paper_2011_07978_amd import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _fields():
+    return [("small", synth.field_small(300)),
+            ("mech53", synth.subsample(synth.field_mapped(30000, seed=11),
+                                       np.arange(0, 30000, 97)))]
+
+
+@pytest.mark.parametrize("name,field", _fields())
+def test_rhs_and_jacobian_match_oracle(name, field):
+    from tests.gpu_util import chem_for, dev, host, say
+    mech = synth.mechanism(name)
+    o = Oracle(mech)
+    c = chem_for(mech)
+    n, nn = field.n_cells, mech.n_species + 1
+    say("rhs_jac", name, n)
+    f = torch.zeros(n * nn, dtype=torch.float64, device="cuda")
+    J = torch.zeros(n * nn * nn, dtype=torch.float64, device="cuda")
+    c.eval_rhs_jac(dev(field.T), dev(field.p), dev(field.Y), f, J)
+    torch.cuda.synchronize()
+    f = host(f).reshape(n, nn)
+    J = host(J).reshape(n, nn, nn)
+    worst_f, worst_J = 0.0, 0.0
+    for i in range(n):
+        y = np.concatenate([[field.T[i]], field.Y[:, i]])
+        fo = o.rhs(field.p[i], y)
+        Jo = o.jac_cs(field.p[i], y)
+        sf = np.abs(fo[1:]).max()
+        worst_f = max(worst_f, abs(f[i, 0] - fo[0]) / max(abs(fo[0]), 1e-300),
+                      np.abs(f[i, 1:] - fo[1:]).max() / max(sf, 1e-300))
+        rows = np.abs(Jo).max(axis=1)
+        rows = np.where(rows > 0, rows, 1.0)
+        worst_J = max(worst_J, float((np.abs(J[i] - Jo).max(axis=1) / rows).max()))
+    # Net rates are differences of much larger forward and reverse rates, so the
+    # ~1 ulp differences between the device and host exp/log and the different
+    # summation orders are amplified by that cancellation: 1e-10 of the largest
+    # component is the roundoff floor here, not a modelling difference.
+    assert worst_f <= 1e-10, worst_f
+    assert worst_J <= 1e-10, worst_J
+
+
+@pytest.mark.parametrize("name,field", _fields())
+def test_single_rodas_step_matches_oracle(name, field):
+    from tests.gpu_util import chem_for, dev, host, say
+    mech = synth.mechanism(name)
+    o = Oracle(mech)
+    c = chem_for(mech)
+    n, nn = field.n_cells, mech.n_species + 1
+    for hstep in (1e-12, 1e-9, 1e-7):
+        say("rodas_step", name, n, hstep)
+        yn = torch.zeros(n * nn, dtype=torch.float64, device="cuda")
+        er = torch.zeros(n * nn, dtype=torch.float64, device="cuda")
+        c.rodas_step(dev(field.T), dev(field.p), dev(field.Y), hstep, yn, er)
+        torch.cuda.synchronize()
+        yn = host(yn).reshape(n, nn)
+        er = host(er).reshape(n, nn)
+        for i in range(n):
+            y = np.concatenate([[field.T[i]], field.Y[:, i]])
+            yo, eo, rc = o.rodas4_step(field.p[i], y, hstep)
+            assert rc == 0
+            if not np.all(np.isfinite(yo)):
+                continue
+            scale = np.abs(y) + np.abs(yo) + 1e-12
+            assert np.max(np.abs(yn[i] - yo) / scale) <= 1e-10, (i, hstep)
+            escale = 1e-12 + 1e-8 * np.maximum(np.abs(y), np.abs(yo))
+            assert np.max(np.abs(er[i] - eo) / escale) <= 1e-4, (i, hstep)
