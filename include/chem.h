@@ -121,7 +121,8 @@ typedef struct {
     int64_t steps_rejected;
     int32_t max_cell_steps;   /* largest accepted+rejected count of any cell */
     int32_t reserved;
-    double ms_total;          /* wall time of the call's GPU work (events) */
+    double ms_total;          /* GPU time of the whole call (HIP events on its stream) */
+    double ms_integrate;      /* GPU time of the integration kernel alone */
 } chem_stats;
 
 /* Create a context on HIP device `hip_device`, enqueueing on `hip_stream`

@@ -45,7 +45,7 @@ class Stats(C.Structure):
     _fields_ = [("cells_integrated", C.c_int64), ("cells_mapped", C.c_int64),
                 ("cells_failed", C.c_int64), ("steps_accepted", C.c_int64),
                 ("steps_rejected", C.c_int64), ("max_cell_steps", C.c_int32),
-                ("reserved", C.c_int32), ("ms_total", C.c_double)]
+                ("reserved", C.c_int32), ("ms_total", C.c_double), ("ms_integrate", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

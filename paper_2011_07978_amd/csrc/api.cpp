@@ -65,7 +65,7 @@ struct chem_ctx {
     unsigned long long *d_reftmp = nullptr;
     double *d_snap = nullptr, *d_delta = nullptr;
     unsigned long long *h_stats = nullptr;   // pinned
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
     int occ = 0;
 };
 
@@ -125,7 +125,8 @@ int chem_create(chem_ctx **out, int hip_device, void *hip_stream) {
         hipMalloc((void **)&c->d_stats, 8 * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc((void **)&c->d_small, 80 * sizeof(int)) != hipSuccess ||
         hipMalloc((void **)&c->d_reftmp, sizeof(unsigned long long)) != hipSuccess ||
-        hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+        hipEventCreate(&c->ev2) != hipSuccess || hipEventCreate(&c->ev3) != hipSuccess) {
         chem_destroy(c);
         return CHEM_E_HIP;
     }
@@ -159,6 +160,8 @@ void chem_destroy(chem_ctx *c) {
     if (c->h_stats) (void)hipHostFree(c->h_stats);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->ev2) (void)hipEventDestroy(c->ev2);
+    if (c->ev3) (void)hipEventDestroy(c->ev3);
     delete c;
 }
 
@@ -229,8 +232,7 @@ int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
             if (!isfinite(a[i])) return fail(c, CHEM_E_BAD_MECHANISM, "species %d: non-finite thermo", k);
     }
     // reactions: indices, balance, parameters
-    std::vector<int> tb_slot(R, 0xffff);
-    int ntb = 0;
+    std::vector<int> is_tb(R, 0);
     for (int j = 0; j < R; ++j) {
         int nr = 0, np = 0;
         std::vector<long> bal(E, 0);
@@ -249,17 +251,17 @@ int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
             if (bal[e] != 0) return fail(c, CHEM_E_BAD_MECHANISM, "reaction %d: element %d unbalanced", j, e);
         if (!(m->A[j] > 0.0) || !isfinite(m->A[j]) || !isfinite(m->b[j]) || !isfinite(m->Ea[j]))
             return fail(c, CHEM_E_BAD_MECHANISM, "reaction %d: bad rate parameters", j);
-        if (m->third_body[j]) tb_slot[j] = ntb++;
+        is_tb[j] = m->third_body[j] != 0;
     }
-    std::vector<std::vector<std::pair<int, double>>> eff(ntb);
+    std::vector<std::vector<std::pair<int, double>>> eff(R);
     for (int i = 0; i < m->n_eff; ++i) {
         const int j = m->eff_reaction[i], k = m->eff_species[i];
-        if (j < 0 || j >= R || !m->third_body[j] || k < 0 || k >= N || !(m->eff_value[i] >= 0.0) ||
+        if (j < 0 || j >= R || !is_tb[j] || k < 0 || k >= N || !(m->eff_value[i] >= 0.0) ||
             !isfinite(m->eff_value[i]))
             return fail(c, CHEM_E_BAD_MECHANISM, "bad third-body efficiency %d", i);
-        for (auto &pr : eff[tb_slot[j]])
+        for (auto &pr : eff[j])
             if (pr.first == k) return fail(c, CHEM_E_BAD_MECHANISM, "duplicate efficiency %d", i);
-        eff[tb_slot[j]].push_back({k, m->eff_value[i] - 1.0});
+        eff[j].push_back({k, m->eff_value[i] - 1.0});
     }
 
     HIPCHK(c, hipSetDevice(c->device));
@@ -284,18 +286,6 @@ int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
         W[k] = m->W[k];
         invW[k] = 1.0 / m->W[k];
     }
-    // species -> reactions CSR with net stoichiometric coefficients
-    std::vector<int> sp_ptr(N + 1, 0), sp_ent;
-    for (int k = 0; k < N; ++k) {
-        sp_ptr[k] = (int)sp_ent.size();
-        for (int j = 0; j < R; ++j) {
-            int nu = 0;
-            for (int s = 0; s < 2; ++s) nu -= m->reactants[2 * j + s] == k;
-            for (int s = 0; s < 3; ++s) nu += m->products[3 * j + s] == k;
-            if (nu != 0) sp_ent.push_back((j << 3) | (nu + 4));
-        }
-    }
-    sp_ptr[N] = (int)sp_ent.size();
     // species records
     std::vector<double> spc((size_t)N * SPC_STRIDE, 0.0);
     for (int k = 0; k < N; ++k) {
@@ -303,18 +293,11 @@ int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
         for (int i = 0; i < 14; ++i) r[i] = nasa_t[i * N + k];
         r[14] = W[k];
         r[15] = invW[k];
-        int2 rng = make_int2(sp_ptr[k], sp_ptr[k + 1]);
-        memcpy(&r[16], &rng, sizeof rng);
     }
-    // reactions
+    // reactions; efficiency lists only for third-body reactions with > 3 entries
     std::vector<RxnRec> rxn(R);
-    std::vector<int> tb_ptr(ntb + 1, 0), eff_sp;
+    std::vector<int> tb_ptr(1, 0), eff_sp;
     std::vector<double> eff_am1;
-    for (int t = 0; t < ntb; ++t) {
-        tb_ptr[t] = (int)eff_sp.size();
-        for (auto &pr : eff[t]) { eff_sp.push_back(pr.first); eff_am1.push_back(pr.second); }
-    }
-    tb_ptr[ntb] = (int)eff_sp.size();
     for (int j = 0; j < R; ++j) {
         auto sl = [&](int k) { return k < 0 ? N : k; };
         const int r0 = sl(m->reactants[2 * j]), r1 = sl(m->reactants[2 * j + 1]);
@@ -322,11 +305,30 @@ int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
         int snu = 0;
         for (int s = 0; s < 2; ++s) snu -= m->reactants[2 * j + s] >= 0;
         for (int s = 0; s < 3; ++s) snu += m->products[3 * j + s] >= 0;
-        rxn[j].idx = make_int4(r0 | (r1 << 16), p0 | (p1 << 16), p2 | (tb_slot[j] << 16), snu);
-        rxn[j].lnA = log(m->A[j]);
-        rxn[j].b = m->b[j];
-        rxn[j].EaR = m->Ea[j] / RU_J;
-        rxn[j].pad = 0.0;
+        int tb = TB_NONE;
+        int es[3] = {N, N, N};
+        RxnRec &q = rxn[j];
+        q.eff[0] = q.eff[1] = q.eff[2] = 0.0;
+        if (is_tb[j]) {
+            if (eff[j].size() <= 3) {
+                tb = TB_INLINE;
+                for (size_t i = 0; i < eff[j].size(); ++i) {
+                    es[i] = eff[j][i].first;
+                    q.eff[i] = eff[j][i].second;
+                }
+            } else {
+                tb = TB_LIST0 + (int)tb_ptr.size() - 1;
+                for (auto &pr : eff[j]) { eff_sp.push_back(pr.first); eff_am1.push_back(pr.second); }
+                tb_ptr.push_back((int)eff_sp.size());
+            }
+        }
+        q.idx[0] = r0 | (r1 << 16);
+        q.idx[1] = p0 | (p1 << 16);
+        q.idx[2] = p2 | (tb << 16);
+        q.idx[3] = (snu + 8) | (es[0] << 8) | (es[1] << 16) | (es[2] << 24);
+        q.lnA = log(m->A[j]);
+        q.b = m->b[j];
+        q.EaR = m->Ea[j] / RU_J;
     }
 
     MechDev &M = c->M;
@@ -335,8 +337,7 @@ int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
     M.ldj = (M.n % 2) ? M.n : M.n + 1;
     int rc;
     if ((rc = upload(c, nasa_t, &M.nasa_t)) || (rc = upload(c, W, &M.W)) ||
-        (rc = upload(c, invW, &M.invW)) || (rc = upload(c, sp_ptr, &M.sp_ptr)) ||
-        (rc = upload(c, sp_ent, &M.sp_ent)) || (rc = upload(c, spc, &M.spc)) ||
+        (rc = upload(c, invW, &M.invW)) || (rc = upload(c, spc, &M.spc)) ||
         (rc = upload(c, rxn, &M.rxn)) || (rc = upload(c, tb_ptr, &M.tb_ptr)) ||
         (rc = upload(c, eff_sp, &M.eff_sp)) || (rc = upload(c, eff_am1, &M.eff_am1))) {
         free_mech(c);
@@ -345,7 +346,7 @@ int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
     // LDS layout (doubles)
     int off = 0;
     M.off_J = off; off += M.n * M.ldj;
-    M.off_q = off; off += R;
+    M.off_q = off; off += N + 1;   // production rates (+ sentinel)
     M.off_C = off; off += N + 1;
     M.off_g = off; off += N + 1;
     M.off_h = off; off += N + 1;
@@ -512,7 +513,9 @@ int chem_integrate(chem_ctx *c, int64_t n, double *T, const double *p, double *Y
             grid = c->num_cu * slots;
             if (grid > n) grid = (int)n;
         }
+        if (stats) HIPCHK(c, hipEventRecord(c->ev2, s));
         HIPCHK(c, launch_integrate(c->NP, c->M, c->d_mech, P, c->opt.schedule, grid, s));
+        if (stats) HIPCHK(c, hipEventRecord(c->ev3, s));
         if (flags)
             HIPCHK(c, launch_map_scatter(n, c->N, T, Y, flags, ref_index, c->d_snap, c->d_delta,
                                          c->M.nasa_t, c->M.invW, status, c->d_stats, s));
@@ -522,8 +525,9 @@ int chem_integrate(chem_ctx *c, int64_t n, double *T, const double *p, double *Y
     HIPCHK(c, hipMemcpyAsync(c->h_stats, c->d_stats, 8 * sizeof(unsigned long long),
                              hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
-    float ms = 0.0f;
+    float ms = 0.0f, msi = 0.0f;
     HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    if (n > 0) HIPCHK(c, hipEventElapsedTime(&msi, c->ev2, c->ev3));
     stats->cells_integrated = (int64_t)c->h_stats[0];
     stats->steps_accepted = (int64_t)c->h_stats[1];
     stats->steps_rejected = (int64_t)c->h_stats[2];
@@ -532,6 +536,7 @@ int chem_integrate(chem_ctx *c, int64_t n, double *T, const double *p, double *Y
     stats->cells_mapped = (int64_t)c->h_stats[5];
     stats->reserved = 0;
     stats->ms_total = ms;
+    stats->ms_integrate = msi;
     return (int)std::min<int64_t>(stats->cells_failed, INT32_MAX);
 }
 

@@ -63,7 +63,7 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
     const MechDev &M = *Mp;
     const int N = M.N, R = M.R, n = M.n, ldj = M.ldj;
     double *__restrict__ Jl = lds + M.off_J;
-    double *__restrict__ ql = lds + M.off_q;
+    double *__restrict__ wl = lds + M.off_q;    // production rates omega_k (+ sentinel)
     double *__restrict__ Cl = lds + M.off_C;
     double *__restrict__ gl = lds + M.off_g;
     double *__restrict__ hl = lds + M.off_h;
@@ -79,9 +79,8 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
 
     // species thermo (NASA-7 single range), Horner form
     double cpR = 0.0, hRT = 0.0, gRT = 0.0, dcpR = 0.0, invWk = 0.0, Wk = 0.0;
-    int csr0 = 0, csr1 = 0;
     if (sp) {
-        const double *a = M.spc + k * SPC_STRIDE;
+        const auto *a = gbl(M.spc) + k * SPC_STRIDE;
         const double a1 = a[0], a2 = a[1], a3 = a[2], a4 = a[3], a5 = a[4], a6 = a[5], a7 = a[6];
         const double h2 = a[7], h3 = a[8], h4 = a[9], h5 = a[10];
         const double s3 = a[11], s4 = a[12], s5 = a[13];
@@ -92,9 +91,6 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
         if (JAC) dcpR = a2 + T * (2.0 * a3 + T * (3.0 * a4 + T * (4.0 * a5)));
         Wk = a[14];
         invWk = a[15];
-        const int2 rng = *reinterpret_cast<const int2 *>(a + 16);
-        csr0 = rng.x;
-        csr1 = rng.y;
     }
     const double yw = sp ? y * invWk : 0.0;
     const double sumYW = wave_sum(yw);
@@ -109,46 +105,54 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
             cpl[k] = cpR * invWk;
         }
     }
+    if (lane <= N) wl[lane] = 0.0;
     if (JAC) {
         for (int i = lane; i < n * ldj; i += 64) Jl[i] = 0.0;
         if (lane < n) tbl[lane] = 0.0;
     }
     __syncthreads();
 
-    // reaction pass
+    // reaction pass: rates of progress scattered to the production rates of
+    // their reactant and product slots (LDS float atomics; missing slots hit
+    // the sentinel entry N)
     const double ln_patm_RT = log(P_ATM / (RU_ERG * T));
-#pragma unroll 1
-    for (int j = lane; j < R; j += 64) {
-        const RxnRec &rec = M.rxn[j];
-        const int4 ix = rec.idx;
-        const int r0 = ix.x & 0xffff, r1 = (int)((unsigned)ix.x >> 16);
-        const int p0 = ix.y & 0xffff, p1 = (int)((unsigned)ix.y >> 16);
-        const int p2 = ix.z & 0xffff, tb = (int)((unsigned)ix.z >> 16);
+    const auto *rxn = gbl(M.rxn);
+    auto reaction = [&](const int j, const bool valid) {
+        const auto &rec = rxn[j];
+        const int ix0 = rec.idx[0], ix1 = rec.idx[1], ix2 = rec.idx[2], ix3 = rec.idx[3];
+        const int r0 = ix0 & 0xffff, r1 = (int)((unsigned)ix0 >> 16);
+        const int p0 = ix1 & 0xffff, p1 = (int)((unsigned)ix1 >> 16);
+        const int p2 = ix2 & 0xffff, tb = (int)((unsigned)ix2 >> 16);
+        const double snu = (double)((ix3 & 0xff) - 8);
+        const int es0 = (ix3 >> 8) & 0xff, es1 = (ix3 >> 16) & 0xff;
+        const int es2 = (int)((unsigned)ix3 >> 24);
         const double Cr0 = Cl[r0], Cr1 = Cl[r1], Cp0 = Cl[p0], Cp1 = Cl[p1], Cp2 = Cl[p2];
         const double dG = -gl[r0] - gl[r1] + gl[p0] + gl[p1] + gl[p2];
         const double bj = rec.b, EaRj = rec.EaR;
         const double ln_kf = rec.lnA + bj * lnT - EaRj * invT;
-        const double ln_Kc = -dG + (double)ix.w * ln_patm_RT;
+        const double ln_Kc = -dG + snu * ln_patm_RT;
         const double kf = exp(ln_kf);
         const double kr = exp(ln_kf - ln_Kc);
         const double Pf = Cr0 * Cr1;
         const double Pr = Cp0 * Cp1 * Cp2;
-        const bool tbr = tb != 0xffff;
-        double m = 1.0;
-        int e0 = 0, e1 = 0;
-        if (tbr) {
-            e0 = M.tb_ptr[tb];
-            e1 = M.tb_ptr[tb + 1];
-            m = Ctot;
-            for (int e = e0; e < e1; ++e) m += M.eff_am1[e] * Cl[M.eff_sp[e]];
+        const double e0v = rec.eff[0], e1v = rec.eff[1], e2v = rec.eff[2];
+        double m = tb == TB_NONE ? 1.0 : Ctot + e0v * Cl[es0] + e1v * Cl[es1] + e2v * Cl[es2];
+        if (tb >= TB_LIST0) {
+            const int e1 = M.tb_ptr[tb - TB_LIST0 + 1];
+            for (int e = M.tb_ptr[tb - TB_LIST0]; e < e1; ++e) m += M.eff_am1[e] * Cl[M.eff_sp[e]];
         }
-        const double Delta = kf * Pf - kr * Pr;
-        ql[j] = m * Delta;
+        const double Delta = valid ? kf * Pf - kr * Pr : 0.0;
+        const double q = m * Delta;
+        lds_add(wl + r0, -q);
+        lds_add(wl + r1, -q);
+        lds_add(wl + p0, q);
+        lds_add(wl + p1, q);
+        lds_add(wl + p2, q);
         if (JAC) {
             const double dlnkf = bj * invT + EaRj * invT * invT;
             const double dH = -hl[r0] - hl[r1] + hl[p0] + hl[p1] + hl[p2];
-            const double dlnkr = dlnkf - (dH - (double)ix.w) * invT;
-            const double mkf = m * kf, mkr = m * kr;
+            const double dlnkr = dlnkf - (dH - snu) * invT;
+            const double mkf = valid ? m * kf : 0.0, mkr = valid ? m * kr : 0.0;
             const double dqdT = mkf * dlnkf * Pf - mkr * dlnkr * Pr;
             const int sl[5] = {r0, r1, p0, p1, p2};
             const double ds[5] = {mkf * Cr1, mkf * Cr0, -mkr * Cp1 * Cp2, -mkr * Cp0 * Cp2,
@@ -163,26 +167,34 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
 #pragma unroll
                 for (int b = 0; b < 5; ++b)
                     if (sl[b] < N) lds_add(row + 1 + sl[b], nu * ds[b]);
-                if (tbr) {
-                    lds_add(tbl + sa + 1, nu * Delta);
-                    for (int e = e0; e < e1; ++e)
-                        lds_add(row + 1 + M.eff_sp[e], nu * M.eff_am1[e] * Delta);
+                if (tb != TB_NONE) {
+                    const double nd = nu * Delta;
+                    lds_add(tbl + sa + 1, nd);
+                    if (es0 < N) lds_add(row + 1 + es0, nd * e0v);
+                    if (es1 < N) lds_add(row + 1 + es1, nd * e1v);
+                    if (es2 < N) lds_add(row + 1 + es2, nd * e2v);
+                    if (tb >= TB_LIST0) {
+                        const int e1 = M.tb_ptr[tb - TB_LIST0 + 1];
+                        for (int e = M.tb_ptr[tb - TB_LIST0]; e < e1; ++e)
+                            lds_add(row + 1 + M.eff_sp[e], nd * M.eff_am1[e]);
+                    }
                 }
             }
         }
+    };
+    // two reactions per trip, both evaluated unconditionally (the second is a
+    // masked duplicate past the end), so their load, exp and LDS latencies
+    // overlap
+#pragma unroll 1
+    for (int j = lane; j < R; j += 128) {
+        const bool v2 = j + 64 < R;
+        reaction(j, true);
+        reaction(v2 ? j + 64 : j, v2);
     }
     __syncthreads();
 
-    // species pass: omega_k by the species -> reaction CSR, in reaction order
-    double fk = 0.0;
-    if (sp) {
-        double om = 0.0;
-        for (int e = csr0; e < csr1; ++e) {
-            const int ent = M.sp_ent[e];
-            om += (double)((ent & 7) - 4) * ql[ent >> 3];
-        }
-        fk = Wk * om / rho;
-    }
+    // species: dY_k/dt = W_k omega_k / rho; dT/dt = -sum_k H_k omega_k / (rho cp)
+    const double fk = sp ? Wk * wl[k] / rho : 0.0;
     const double hs = wave_sum(sp ? hRT * invWk * fk : 0.0);
     const double cps = wave_sum(sp ? y * cpR * invWk : 0.0);
     const double fT = -T * hs / cps;
@@ -195,18 +207,33 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
         if (sp) {
             double *row = Jl + lane * ldj;
             const double tbk = tbl[lane];
-            double s = 0.0;
-            for (int l = 0; l < N; ++l) s += (row[1 + l] + tbk) * Cl[l];
+            double s0 = 0.0, s1 = 0.0;
+            int l = 0;
+#pragma unroll 4
+            for (; l + 1 < N; l += 2) {
+                s0 += (row[1 + l] + tbk) * Cl[l];
+                s1 += (row[2 + l] + tbk) * Cl[l + 1];
+            }
+            if (l < N) s0 += (row[1 + l] + tbk) * Cl[l];
+            const double s = s0 + s1;
             const double cst = fk * Wbar - Wk * Wbar * s / rho;
-            for (int i = 0; i < N; ++i) row[1 + i] = M.invW[i] * (Wk * (row[1 + i] + tbk) + cst);
+            const auto *iw = gbl(M.invW);
+#pragma unroll 8
+            for (int i = 0; i < N; ++i) row[1 + i] = iw[i] * (Wk * (row[1 + i] + tbk) + cst);
             row[0] = Wk / rho * (row[0] - s * invT) + fk * invT;
         }
         __syncthreads();
         // temperature row: J_T,c = -(sum_k e_k J_kc)/cp - f_T dcp/dy_c / cp
         if (lane < n) {
-            double acc = 0.0;
-            for (int kk = 0; kk < N; ++kk) acc += el[kk] * Jl[(kk + 1) * ldj + lane];
-            acc *= T;
+            double a0 = 0.0, a1 = 0.0;
+            int kk = 0;
+#pragma unroll 4
+            for (; kk + 1 < N; kk += 2) {
+                a0 += el[kk] * Jl[(kk + 1) * ldj + lane];
+                a1 += el[kk + 1] * Jl[(kk + 2) * ldj + lane];
+            }
+            if (kk < N) a0 += el[kk] * Jl[(kk + 1) * ldj + lane];
+            const double acc = (a0 + a1) * T;
             double v;
             if (lane == 0) v = -(cpf + acc) / cps - fT * dcps / cps;
             else v = -acc / cps - fT * cpl[lane - 1] / cps;

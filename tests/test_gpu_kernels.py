@@ -65,13 +65,25 @@ def test_single_rodas_step_matches_oracle(name, field):
         torch.cuda.synchronize()
         yn = host(yn).reshape(n, nn)
         er = host(er).reshape(n, nn)
+        worst = 0.0
         for i in range(n):
             y = np.concatenate([[field.T[i]], field.Y[:, i]])
             yo, eo, rc = o.rodas4_step(field.p[i], y, hstep)
             assert rc == 0
             if not np.all(np.isfinite(yo)):
                 continue
+            # one step solves six systems with M = I/(gamma h) - J: the two
+            # implementations agree to roundoff amplified by cond(M)
+            Mo = np.eye(nn) / (0.25 * hstep) - o.jac(field.p[i], y)
+            bound = max(1e-12, 50 * 2.2e-16 * np.linalg.cond(Mo))
             scale = np.abs(y) + np.abs(yo) + 1e-12
-            assert np.max(np.abs(yn[i] - yo) / scale) <= 1e-10, (i, hstep)
-            escale = 1e-12 + 1e-8 * np.maximum(np.abs(y), np.abs(yo))
-            assert np.max(np.abs(er[i] - eo) / escale) <= 1e-4, (i, hstep)
+            r_y = np.max(np.abs(yn[i] - yo) / scale) / bound
+            # the error estimate enters the method only through its normalised
+            # max-norm, compared with 1: that number must agree
+            sc_o = 1e-12 + 1e-8 * np.maximum(np.abs(y), np.abs(yo))
+            sc_g = 1e-12 + 1e-8 * np.maximum(np.abs(y), np.abs(yn[i]))
+            en_o, en_g = np.max(np.abs(eo) / sc_o), np.max(np.abs(er[i]) / sc_g)
+            r_e = abs(en_g - en_o) / (1e-6 * max(1.0, en_o))
+            worst = max(worst, r_y, r_e)
+        print("rodas step", name, hstep, "worst / bound", worst)
+        assert worst <= 1.0
