@@ -47,6 +47,11 @@ def lib():
         L.orc_integrate_cell.restype = C.c_int
         L.orc_rodas4_step.restype = C.c_int
         L.orc_lu.restype = C.c_int
+        L.orc_mlp_param_count.restype = C.c_int64
+        L.orc_bf16.restype = C.c_double
+        L.orc_bf16.argtypes = [C.c_double]
+        L.orc_mlp_loss_grad.restype = C.c_double
+        L.orc_surrogate_cell.restype = C.c_int
         _lib = L
     return _lib
 
@@ -233,6 +238,62 @@ class Oracle:
         Yref_new = Y2[:, ref].copy()
         T3, Y3 = self.map_scatter(T2, Y2, flags, Yref_old, Yref_new)
         return (T3, Y3) + tuple(out[2:])
+
+
+# ----------------------------------------------------------------- surrogate
+MLP_IN, MLP_HID, MLP_OUT = 64, 256, 64
+
+
+def mlp_param_count():
+    return int(lib().orc_mlp_param_count())
+
+
+def bf16(x):
+    return lib().orc_bf16(float(x))
+
+
+def mlp_features(N, T, p, Y, dt):
+    x = np.zeros(MLP_IN)
+    lib().orc_mlp_features(int(N), C.c_double(T), C.c_double(p), _p(_f64(Y)), C.c_double(dt), _p(x))
+    return x
+
+
+def mlp_forward(params, X, nfeat, bf16_emulation=True, want_acts=False):
+    P = np.ascontiguousarray(params, np.float32)
+    X = _f64(X)
+    n = X.shape[0]
+    out = np.zeros((n, MLP_OUT))
+    acts = np.zeros((n, 4, MLP_HID)) if want_acts else None
+    lib().orc_mlp_forward(P.ctypes.data_as(C.POINTER(C.c_float)), C.c_int64(n), int(nfeat), _p(X),
+                          int(bool(bf16_emulation)), _p(out),
+                          _p(acts) if acts is not None else None, None)
+    return (out, acts) if want_acts else out
+
+
+def mlp_loss_grad(params, X, target, nfeat, nout, bf16_emulation=False):
+    P = np.ascontiguousarray(params, np.float32)
+    X, target = _f64(X), _f64(target)
+    g = np.zeros(mlp_param_count())
+    loss = lib().orc_mlp_loss_grad(P.ctypes.data_as(C.POINTER(C.c_float)), C.c_int64(X.shape[0]),
+                                   int(nfeat), int(nout), _p(X), _p(target),
+                                   int(bool(bf16_emulation)), _p(g))
+    return loss, g
+
+
+def project(o, dY):
+    d = _f64(dY).copy()
+    lib().orc_project(o.h, _p(d))
+    return d
+
+
+def surrogate_cell(o, params, p, T, Y, dt, tau_T=0.5, y_min=-1e-10, margin=0.0):
+    P = np.ascontiguousarray(params, np.float32)
+    Tc = C.c_double(T)
+    Yc = _f64(Y).copy()
+    ok = lib().orc_surrogate_cell(o.h, P.ctypes.data_as(C.POINTER(C.c_float)), C.c_double(p),
+                                  C.byref(Tc), _p(Yc), C.c_double(dt), C.c_double(tau_T),
+                                  C.c_double(y_min), C.c_double(margin))
+    return bool(ok), Tc.value, Yc
 
 
 def rodas4_coefficients():

@@ -134,6 +134,18 @@ void orc_map_scatter(const omech *m, int64_t ncells, double *T, double *Y,
 double orc_temperature_from_enthalpy(const omech *m, double h, const double *Y,
                                      double T_guess, int *iters);
 
+/* learned surrogate (see mlp.c) ------------------------------------------*/
+int64_t orc_mlp_param_count(void);
+double orc_bf16(double x);
+void orc_mlp_features(int N, double T, double p, const double *Y, double dt, double *x);
+void orc_mlp_forward(const float *P, int64_t n, int nfeat, const double *X, int bf16,
+                     double *out, double *acts, double *pre);
+double orc_mlp_loss_grad(const float *P, int64_t n, int nfeat, int nout, const double *X,
+                         const double *target, int bf16, double *grad);
+void orc_project(const omech *m, double *dY);
+int orc_surrogate_cell(const omech *m, const float *P, double p, double *T, double *Y, double dt,
+                       double tau_T, double y_min, double margin);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,141 @@
+"""Pins of the surrogate oracle: bfloat16 rounding, the MLP forward pass,
+backpropagation and the element-conservation projection (CPU only)."""
+import numpy as np
+import pytest
+import torch
+from scipy.special import erf
+
+import oracle
+from oracle import Oracle
+from paper_2011_07978_amd import synth
+
+IN, HID, OUT = 64, 256, 64
+DIMS = [IN, HID, HID, HID, HID, OUT]
+
+
+def random_params(seed=0, nfeat=56, scale=1.0):
+    rng = np.random.default_rng(seed)
+    P = []
+    for l in range(5):
+        ni, no = DIMS[l], DIMS[l + 1]
+        P.append((rng.standard_normal((no, ni)) * scale / np.sqrt(ni)).ravel())
+        P.append(rng.standard_normal(no) * 0.1)
+    mu = np.zeros(IN)
+    sd = np.ones(IN)
+    mu[:nfeat] = rng.standard_normal(nfeat) * 0.1
+    sd[:nfeat] = rng.uniform(0.5, 2.0, nfeat)
+    P += [mu, sd, np.zeros(IN), np.ones(IN), -np.ones(IN) * 1e9, np.ones(IN) * 1e9]
+    P = np.concatenate(P).astype(np.float32)
+    assert P.size == oracle.mlp_param_count()
+    return P
+
+
+def unpack(P):
+    out, o = [], 0
+    for l in range(5):
+        ni, no = DIMS[l], DIMS[l + 1]
+        W = P[o:o + no * ni].reshape(no, ni).astype(np.float64)
+        o += no * ni
+        b = P[o:o + no].astype(np.float64)
+        o += no
+        out.append((W, b))
+    nb = P[o:].reshape(6, IN).astype(np.float64)
+    return out, nb
+
+
+def test_bf16_rounding_matches_torch():
+    rng = np.random.default_rng(5)
+    vals = np.concatenate([rng.standard_normal(2000) * 10.0 ** rng.integers(-8, 8, 2000),
+                           [0.0, -0.0, 1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, 65504.0, 1e-40]])
+    ref = torch.tensor(vals.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    got = np.array([oracle.bf16(v) for v in vals.astype(np.float32)])
+    assert np.array_equal(got, ref)
+
+
+def test_forward_fp64_matches_matrix_products():
+    P = random_params(1)
+    layers, nb = unpack(P)
+    rng = np.random.default_rng(2)
+    X = np.zeros((7, IN))
+    X[:, :56] = rng.standard_normal((7, 56))
+    out = oracle.mlp_forward(P, X, 56, bf16_emulation=False)
+    h = (X - nb[0]) / nb[1]
+    h[:, 56:] = 0.0
+    for l, (W, b) in enumerate(layers):
+        z = h @ W.T + b
+        h = 0.5 * z * (1 + erf(z / np.sqrt(2))) if l < 4 else z
+    np.testing.assert_allclose(out, h, rtol=1e-12, atol=1e-12)
+
+
+def test_bf16_forward_close_to_fp64():
+    P = random_params(3)
+    X = np.zeros((5, IN))
+    X[:, :56] = np.random.default_rng(4).standard_normal((5, 56))
+    a = oracle.mlp_forward(P, X, 56, bf16_emulation=False)
+    b = oracle.mlp_forward(P, X, 56, bf16_emulation=True)
+    err = np.abs(a - b).max() / np.abs(a).max()
+    assert 1e-5 < err < 5e-2      # bfloat16 has an 8-bit mantissa
+
+
+def test_backprop_matches_central_differences():
+    P = random_params(6)
+    rng = np.random.default_rng(7)
+    X = np.zeros((4, IN))
+    X[:, :56] = rng.standard_normal((4, 56))
+    target = rng.standard_normal((4, OUT))
+    loss, g = oracle.mlp_loss_grad(P, X, target, 56, 54, bf16_emulation=False)
+    nparam = P.size - 6 * IN
+    idx = np.concatenate([rng.choice(nparam, 40, replace=False),
+                          [0, 64 * 256 + 3, nparam - 1, nparam - 64 - 5]])
+    for i in idx:
+        eps = 1e-3 * max(1.0, abs(float(P[i])))
+        Pp, Pm = P.copy(), P.copy()
+        Pp[i] = np.float32(P[i] + eps)
+        Pm[i] = np.float32(P[i] - eps)
+        d = float(Pp[i]) - float(Pm[i])
+        lp, _ = oracle.mlp_loss_grad(Pp, X, target, 56, 54)
+        lm, _ = oracle.mlp_loss_grad(Pm, X, target, 56, 54)
+        fd = (lp - lm) / d
+        assert abs(fd - g[i]) <= 1e-6 * max(1e-3, abs(g[i])) + 1e-9, (i, fd, g[i])
+    assert np.all(g[nparam:] == 0)
+
+
+def test_projection_properties():
+    mech = synth.mechanism("mech53")
+    o = Oracle(mech)
+    E = (mech.composition.T / mech.W[None, :])          # [elements, species]
+    rng = np.random.default_rng(8)
+    for _ in range(5):
+        dY = rng.standard_normal(mech.n_species) * 1e-3
+        d1 = oracle.project(o, dY)
+        assert np.abs(E @ d1).max() <= 1e-15 * np.abs(E).max() * np.abs(dY).max() * 100
+        assert abs(d1.sum()) <= 1e-15
+        np.testing.assert_allclose(oracle.project(o, d1), d1, atol=1e-19)      # idempotent
+        # the correction lies in the row space of E (minimum-norm projection)
+        corr = dY - d1
+        lam, *_ = np.linalg.lstsq(E.T, corr, rcond=None)
+        np.testing.assert_allclose(E.T @ lam, corr, atol=1e-17)
+        assert np.linalg.norm(d1) <= np.linalg.norm(dY)
+
+
+def test_surrogate_cell_gate_and_conservation():
+    mech = synth.mechanism("mech53")
+    o = Oracle(mech)
+    N = mech.n_species
+    P = random_params(9, scale=1e-3)       # tiny network: small increments
+    layers, nb = unpack(P)
+    f = synth.field_mapped(2000, seed=4)
+    i = int(np.nonzero(f.cls == 1)[0][0])
+    T, Y = f.T[i], f.Y[:, i].copy()
+    ok, T1, Y1 = oracle.surrogate_cell(o, P, f.p[i], T, Y, 1e-6, tau_T=1e9, y_min=-1.0)
+    assert ok
+    E = (mech.composition.T / mech.W[None, :])
+    assert np.abs(E @ (Y1 - Y)).max() <= 1e-15
+    assert abs(o.enthalpy(T1, Y1) - o.enthalpy(T, Y)) <= 1e-12 * o.cp(T, Y) * T
+    # out-of-box input is rejected
+    P2 = P.copy()
+    base = P2.size - 6 * IN
+    P2[base + 4 * IN: base + 5 * IN] = 0.0      # xmin
+    P2[base + 5 * IN: base + 6 * IN] = 0.0      # xmax: empty box
+    ok, T2, Y2 = oracle.surrogate_cell(o, P2, f.p[i], T, Y, 1e-6, tau_T=1e9, y_min=-1.0)
+    assert not ok and T2 == T and np.array_equal(Y2, Y)
