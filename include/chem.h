@@ -54,7 +54,16 @@ enum {
     CHEM_CELL_H_UNDERFLOW = 2, /* step fell below hmin_frac * dt */
     CHEM_CELL_NONFINITE = 3,   /* accepted state not finite */
     CHEM_CELL_BAD_INPUT = 4,   /* T <= 0, p <= 0 or non-finite input; cell untouched */
-    CHEM_CELL_MAPPED = 5       /* cell took the reference's increment */
+    CHEM_CELL_MAPPED = 5,      /* cell took the reference's increment */
+    CHEM_CELL_SURROGATE = 6    /* cell was advanced by the learned surrogate */
+};
+
+/* routing flags (uint8 per cell) */
+enum {
+    CHEM_FLAG_SOLVE = 0,       /* integrate (the surrogate may take it) */
+    CHEM_FLAG_REFERENCE = 1,   /* reference cell of the mapping: always integrated */
+    CHEM_FLAG_MAPPED = 2,      /* takes the reference's increment */
+    CHEM_FLAG_SURROGATE = 3    /* advanced by the surrogate; not integrated */
 };
 
 /* scheduling of cells onto wavefronts */
@@ -123,7 +132,46 @@ typedef struct {
     int32_t reserved;
     double ms_total;          /* GPU time of the whole call (HIP events on its stream) */
     double ms_integrate;      /* GPU time of the integration kernel alone */
+    int64_t cells_surrogate;  /* cells the surrogate advanced (gate passed) */
+    int64_t cells_rejected;   /* cells the gate sent back to the Rosenbrock solver */
+    double ms_surrogate;      /* GPU time of the surrogate pass (inference + gate) */
 } chem_stats;
+
+/* Learned surrogate (not part of the paper; its relatives there are the
+ * tabulation methods ISAT/TDAC of Sec. 1 and Sec. 5).  A multilayer
+ * perceptron advances a cell by dt:
+ *   features x = (ln T, ln p, Y_1..Y_N, ln dt), normalised with the training
+ *     set's mean and standard deviation, zero-padded to 64;
+ *   four hidden layers of 256 with GELU (erf form); output 64, of which the
+ *     first N+1 are the normalised increments (dY_1..dY_N, dT).
+ * Weights and activations are bfloat16 (round to nearest even), products
+ * accumulate in FP32 on the matrix cores, biases and GELU in FP32.
+ * Parameter blob (float32, chem_surrogate_param_count() entries): layer by
+ * layer W_l [out x in] row-major then b_l [out] (dims 64-256-256-256-256-64),
+ * then six blocks of 64: mu_x, sd_x (feature normalisation), mu_o, sd_o
+ * (output de-normalisation), xmin, xmax (training range of the raw features).
+ * Each prediction dY is projected onto element conservation,
+ *   dY <- dY - E^T (E E^T)^-1 E dY,  E_ek = a_ek / W_k,
+ * and T' solves h(T', Y + dY) = h(T, Y).  The gate (chem_gate_params) sends a
+ * cell back to the Rosenbrock solver unless every raw feature lies in
+ * [xmin - margin*(xmax - xmin), xmax + margin*(xmax - xmin)], every
+ * Y_k + dY_k >= y_min and |T + dT - T'| <= tau_T.
+ * Available for N <= 61 species and E <= 8 elements with E E^T invertible
+ * (otherwise the surrogate entry points return CHEM_E_UNIMPL). */
+typedef struct {
+    int32_t epochs;       /* passes over the samples (default 8) */
+    int32_t batch;        /* rows per Adam step: multiple of 64, <= 65536 (default 4096) */
+    double lr_max;        /* cosine learning-rate schedule from lr_max ... (default 2e-3) */
+    double lr_min;        /* ... to lr_min at the last step (default 2e-5) */
+    uint64_t seed;        /* weight initialisation and shuffling (default 0) */
+    int32_t verbose;      /* 1: loss of every epoch on stderr */
+} chem_train_params;
+
+typedef struct {
+    double tau_T;         /* K (default 0.5) */
+    double y_min;         /* (default -1e-10) */
+    double margin;        /* fraction of each feature's training span (default 0) */
+} chem_gate_params;
 
 /* Create a context on HIP device `hip_device`, enqueueing on `hip_stream`
  * (a hipStream_t; NULL = the device's null stream).  *out receives the
@@ -169,6 +217,7 @@ int chem_map_reference(chem_ctx *ctx, int64_t n_cells, const double *T, const do
  *   flags [n] device (nullable): cells flagged 2 are not integrated; they take
  *     Y += Y_ref(after) - Y_ref(before) and T from enthalpy conservation, with
  *     the reference cell *ref_index (device int64, required with flags).
+ *     Cells flagged 3 (surrogate) are left alone.
  *   h [n] device in/out (nullable): initial step (<= 0 means dt); on return the
  *     step size proposed after each cell's last accepted step.
  *   cost [n] device uint32 in/out (nullable): in, the previous call's per-cell
@@ -180,6 +229,94 @@ int chem_map_reference(chem_ctx *ctx, int64_t n_cells, const double *T, const do
 int chem_integrate(chem_ctx *ctx, int64_t n_cells, double *T, const double *p, double *Y,
                    double dt, const uint8_t *flags, const int64_t *ref_index, double *h,
                    uint32_t *cost, uint8_t *status, int32_t *steps, chem_stats *stats);
+
+/* chem_integrate with the learned surrogate first: every cell whose flag is
+ * CHEM_FLAG_SOLVE is offered to the surrogate; cells the gate accepts are
+ * updated in place and flagged CHEM_FLAG_SURROGATE (flags is device in/out
+ * and required; zero-fill it when no mapping is used), all other cells are
+ * handled as by chem_integrate.  ref_index may be NULL when no flag is 1 or 2.
+ * Status CHEM_CELL_SURROGATE marks surrogate cells.  Requires parameters
+ * (chem_surrogate_train, _set_params or _load).  With a warm workspace (a
+ * previous call with at least min(n, 262144) cells) it allocates nothing. */
+int chem_integrate_surrogate(chem_ctx *ctx, int64_t n_cells, double *T, const double *p, double *Y,
+                             double dt, uint8_t *flags, const int64_t *ref_index,
+                             const chem_gate_params *gate, double *h, uint32_t *cost,
+                             uint8_t *status, int32_t *steps, chem_stats *stats);
+
+void chem_default_train_params(chem_train_params *t);
+void chem_default_gate_params(chem_gate_params *g);
+int64_t chem_surrogate_param_count(void);
+
+/* Train the surrogate on n solver-generated pairs (T0, Y0) -> (T1, Y1) over
+ * per-sample steps dt (all device arrays: T0, p, dt, T1 [n]; Y0, Y1 [N*n]
+ * species-major).  Computes the normalisation and box from the data, draws
+ * the initial weights from seed, then runs epochs x floor(n / batch) Adam
+ * steps (beta 0.9/0.999, FP32 master weights) on the mean-squared error of
+ * the normalised outputs.  loss_history (host, nullable) receives the mean
+ * loss of each epoch.  Synchronous; allocates. */
+int chem_surrogate_train(chem_ctx *ctx, int64_t n, const double *T0, const double *p,
+                         const double *Y0, const double *dt, const double *T1, const double *Y1,
+                         const chem_train_params *tp, float *loss_history);
+/* Copy the parameter blob to / from host memory (synchronous).  set_params
+ * rejects non-finite entries and non-positive normalisation scales. */
+int chem_surrogate_get_params(chem_ctx *ctx, float *host);
+int chem_surrogate_set_params(chem_ctx *ctx, const float *host);
+/* Parameter file: 8-byte magic "LCHSUR01", int32 N, int32 E, int64 count,
+ * then the float32 blob (host byte order).  load checks N and E. */
+int chem_surrogate_save(chem_ctx *ctx, const char *path);
+int chem_surrogate_load(chem_ctx *ctx, const char *path);
+/* Raw network outputs (normalised) for n cells: out [n][64] float32 device,
+ * row-major.  dt [n] device.  Kernel-level check of inference. */
+int chem_surrogate_forward(chem_ctx *ctx, int64_t n, const double *T, const double *p,
+                           const double *Y, const double *dt, float *out);
+/* Mean-squared-error loss and its gradient (host, float32, blob layout, the
+ * normalisation blocks left at zero) over n pairs (64 <= n <= 65536, n a
+ * multiple of 64) with the current parameters and normalisation.
+ * Kernel-level check of backpropagation. */
+int chem_surrogate_loss_grad(chem_ctx *ctx, int64_t n, const double *T0, const double *p,
+                             const double *Y0, const double *dt, const double *T1,
+                             const double *Y1, float *grad, double *loss);
+
+/* ---- graph capture and launch tuning.  The paper keeps the balancing
+ * overhead (preprocessing, balancing and update stages) below 1 % of the
+ * chemistry time (Appendix B); on one GPU that overhead is the host-side
+ * launch cost of the mapping and queue kernels, which replaying a recorded
+ * HIP graph removes, and the queue's launch shape, which chem_autotune picks. */
+typedef struct chem_graph chem_graph;
+
+/* Record, instead of run, the calls made on ctx until chem_graph_end
+ * (chem_map_reference, chem_integrate and chem_integrate_surrogate without
+ * stats).  The context's stream must be a created stream, not the null
+ * stream.  Everything those calls allocate must exist beforehand:
+ * chem_reserve(n), one eager chem_map_reference with the same streams, and for
+ * the surrogate one eager call with at least min(n, 262144) cells; a call that
+ * would allocate or synchronise returns CHEM_E_CAPTURE_UNSAFE and
+ * chem_graph_end then fails. */
+int chem_graph_begin(chem_ctx *ctx);
+/* End the recording and instantiate it; *out is owned by the caller. */
+int chem_graph_end(chem_ctx *ctx, chem_graph **out);
+/* Replay the recorded work on the context's stream (asynchronous).  The
+ * graph reads and writes the very device arrays the recorded calls named. */
+int chem_graph_launch(chem_ctx *ctx, const chem_graph *g);
+void chem_graph_destroy(chem_graph *g);
+
+typedef struct {
+    int32_t schedule, queue_chunk, slots_per_cu;
+    double ms;            /* GPU time of one chem_integrate call with these options */
+} chem_tune_entry;
+
+/* Time launch configurations on copies of a sample state and keep the fastest
+ * in the context's options: the plain launch, and the work queue with
+ * queue_chunk in {1, 2, 4, 8} and slots_per_cu in {occupancy / 2, occupancy}
+ * (occupancy = workgroups of the integration kernel that fit on one CU).  One
+ * untimed pass first records the per-cell cost that orders the queue.
+ * T, p, Y, flags, ref_index as for chem_integrate (device, read only).
+ * results (host, nullable) receives up to max_results entries in the order
+ * above, *n_results (nullable) their count.  Synchronous; allocates scratch
+ * for one copy of the state. */
+int chem_autotune(chem_ctx *ctx, int64_t n_cells, const double *T, const double *p, const double *Y,
+                  double dt, const uint8_t *flags, const int64_t *ref_index,
+                  chem_tune_entry *results, int32_t max_results, int32_t *n_results);
 
 /* Evaluate f(y) and the analytic Jacobian for n cells (kernel-level check of
  * the rate and Jacobian code of the integrator).  T, p [n], Y [N*n] device;

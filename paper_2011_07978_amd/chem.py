@@ -16,7 +16,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libchem.so")
 
 CHEM_SCHED_PLAIN, CHEM_SCHED_QUEUE = 0, 1
-CELL_OK, CELL_MAX_STEPS, CELL_H_UNDERFLOW, CELL_NONFINITE, CELL_BAD_INPUT, CELL_MAPPED = range(6)
+(CELL_OK, CELL_MAX_STEPS, CELL_H_UNDERFLOW, CELL_NONFINITE, CELL_BAD_INPUT, CELL_MAPPED,
+ CELL_SURROGATE) = range(7)
+FLAG_SOLVE, FLAG_REFERENCE, FLAG_MAPPED, FLAG_SURROGATE = range(4)
 
 _d = C.POINTER(C.c_double)
 _i32 = C.POINTER(C.c_int32)
@@ -45,16 +47,39 @@ class Stats(C.Structure):
     _fields_ = [("cells_integrated", C.c_int64), ("cells_mapped", C.c_int64),
                 ("cells_failed", C.c_int64), ("steps_accepted", C.c_int64),
                 ("steps_rejected", C.c_int64), ("max_cell_steps", C.c_int32),
-                ("reserved", C.c_int32), ("ms_total", C.c_double), ("ms_integrate", C.c_double)]
+                ("reserved", C.c_int32), ("ms_total", C.c_double), ("ms_integrate", C.c_double),
+                ("cells_surrogate", C.c_int64), ("cells_rejected", C.c_int64),
+                ("ms_surrogate", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class TrainParams(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr_max", C.c_double),
+                ("lr_min", C.c_double), ("seed", C.c_uint64), ("verbose", C.c_int32)]
+
+
+class GateParams(C.Structure):
+    _fields_ = [("tau_T", C.c_double), ("y_min", C.c_double), ("margin", C.c_double)]
+
+
+class TuneEntry(C.Structure):
+    _fields_ = [("schedule", C.c_int32), ("queue_chunk", C.c_int32), ("slots_per_cu", C.c_int32),
+                ("ms", C.c_double)]
+
+
 EXPORTS = ["chem_create", "chem_destroy", "chem_set_stream", "chem_last_error",
            "chem_set_mechanism", "chem_max_species", "chem_set_options", "chem_get_options",
            "chem_default_options", "chem_reserve", "chem_map_reference", "chem_integrate",
-           "chem_eval_rhs_jac", "chem_rodas_step"]
+           "chem_eval_rhs_jac", "chem_rodas_step", "chem_integrate_surrogate",
+           "chem_default_train_params", "chem_default_gate_params", "chem_surrogate_param_count",
+           "chem_surrogate_train", "chem_surrogate_get_params", "chem_surrogate_set_params",
+           "chem_surrogate_save", "chem_surrogate_load", "chem_surrogate_forward",
+           "chem_surrogate_loss_grad", "chem_graph_begin", "chem_graph_end", "chem_graph_launch",
+           "chem_graph_destroy", "chem_autotune"]
+_VOID = ("chem_destroy", "chem_default_options", "chem_last_error", "chem_default_train_params",
+         "chem_default_gate_params", "chem_surrogate_param_count", "chem_graph_destroy")
 
 _lib = None
 
@@ -86,8 +111,32 @@ def load_library(path: str = LIB_PATH):
                                  C.POINTER(Stats)]
     L.chem_eval_rhs_jac.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp]
     L.chem_rodas_step.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_double, vp, vp]
+    L.chem_integrate_surrogate.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_double, vp, vp,
+                                           C.POINTER(GateParams), vp, vp, vp, vp, C.POINTER(Stats)]
+    L.chem_default_train_params.argtypes = [C.POINTER(TrainParams)]
+    L.chem_default_train_params.restype = None
+    L.chem_default_gate_params.argtypes = [C.POINTER(GateParams)]
+    L.chem_default_gate_params.restype = None
+    L.chem_surrogate_param_count.argtypes = []
+    L.chem_surrogate_param_count.restype = C.c_int64
+    L.chem_surrogate_train.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp,
+                                       C.POINTER(TrainParams), vp]
+    L.chem_surrogate_get_params.argtypes = [vp, vp]
+    L.chem_surrogate_set_params.argtypes = [vp, vp]
+    L.chem_surrogate_save.argtypes = [vp, C.c_char_p]
+    L.chem_surrogate_load.argtypes = [vp, C.c_char_p]
+    L.chem_surrogate_forward.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp]
+    L.chem_surrogate_loss_grad.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp, vp,
+                                           C.POINTER(C.c_double)]
+    L.chem_graph_begin.argtypes = [vp]
+    L.chem_graph_end.argtypes = [vp, C.POINTER(vp)]
+    L.chem_graph_launch.argtypes = [vp, vp]
+    L.chem_graph_destroy.argtypes = [vp]
+    L.chem_graph_destroy.restype = None
+    L.chem_autotune.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_double, vp, vp,
+                                C.POINTER(TuneEntry), C.c_int32, C.POINTER(C.c_int32)]
     for name in EXPORTS:
-        if name not in ("chem_destroy", "chem_default_options", "chem_last_error"):
+        if name not in _VOID:
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -212,3 +261,115 @@ class Chem:
         self._check(self.L.chem_rodas_step(self.h, T.shape[0], _ptr(T), _ptr(p), _ptr(Y), float(h),
                                            _ptr(ynew), _ptr(err)), "chem_rodas_step")
         return ynew, err
+
+    # ------------------------------------------------------------ surrogate
+    def integrate_surrogate(self, T, p, Y, dt, flags, ref_index=None, gate=None, h=None,
+                            cost=None, status=None, steps=None, stats=False):
+        """chem_integrate_surrogate; gate: dict of chem_gate_params fields."""
+        g = GateParams()
+        self.L.chem_default_gate_params(C.byref(g))
+        for key, v in (gate or {}).items():
+            setattr(g, key, v)
+        st = Stats() if stats else None
+        rc = self.L.chem_integrate_surrogate(self.h, T.shape[0], _ptr(T), _ptr(p), _ptr(Y),
+                                             float(dt), _ptr(flags), _ptr(ref_index), C.byref(g),
+                                             _ptr(h), _ptr(cost), _ptr(status), _ptr(steps),
+                                             C.byref(st) if st is not None else None)
+        self._check(rc, "chem_integrate_surrogate")
+        return st.as_dict() if st is not None else None
+
+    def surrogate_param_count(self) -> int:
+        return int(self.L.chem_surrogate_param_count())
+
+    def surrogate_train(self, T0, p, Y0, dt, T1, Y1, **kw):
+        """chem_surrogate_train; returns the per-epoch loss (numpy float32)."""
+        import numpy as np
+        tp = TrainParams()
+        self.L.chem_default_train_params(C.byref(tp))
+        for key, v in kw.items():
+            setattr(tp, key, v)
+        hist = np.zeros(tp.epochs, np.float32)
+        self._check(self.L.chem_surrogate_train(self.h, T0.shape[0], _ptr(T0), _ptr(p), _ptr(Y0),
+                                                _ptr(dt), _ptr(T1), _ptr(Y1), C.byref(tp),
+                                                hist.ctypes.data_as(C.c_void_p)),
+                    "chem_surrogate_train")
+        return hist
+
+    def surrogate_get_params(self):
+        import numpy as np
+        P = np.zeros(self.surrogate_param_count(), np.float32)
+        self._check(self.L.chem_surrogate_get_params(self.h, P.ctypes.data_as(C.c_void_p)),
+                    "chem_surrogate_get_params")
+        return P
+
+    def surrogate_set_params(self, P):
+        import numpy as np
+        P = _np(P, np.float32)
+        if P.size != self.surrogate_param_count():
+            raise ValueError("parameter blob has the wrong size")
+        self._check(self.L.chem_surrogate_set_params(self.h, P.ctypes.data_as(C.c_void_p)),
+                    "chem_surrogate_set_params")
+
+    def surrogate_save(self, path):
+        self._check(self.L.chem_surrogate_save(self.h, os.fsencode(path)), "chem_surrogate_save")
+
+    def surrogate_load(self, path):
+        self._check(self.L.chem_surrogate_load(self.h, os.fsencode(path)), "chem_surrogate_load")
+
+    def surrogate_forward(self, T, p, Y, dt, out=None):
+        n = T.shape[0]
+        if out is None:
+            out = torch.empty((n, 64), dtype=torch.float32, device=T.device)
+        self._check(self.L.chem_surrogate_forward(self.h, n, _ptr(T), _ptr(p), _ptr(Y), _ptr(dt),
+                                                  _ptr(out)), "chem_surrogate_forward")
+        return out
+
+    def surrogate_loss_grad(self, T0, p, Y0, dt, T1, Y1):
+        import numpy as np
+        g = np.zeros(self.surrogate_param_count(), np.float32)
+        loss = C.c_double(0.0)
+        self._check(self.L.chem_surrogate_loss_grad(self.h, T0.shape[0], _ptr(T0), _ptr(p),
+                                                    _ptr(Y0), _ptr(dt), _ptr(T1), _ptr(Y1),
+                                                    g.ctypes.data_as(C.c_void_p), C.byref(loss)),
+                    "chem_surrogate_loss_grad")
+        return float(loss.value), g
+
+    # ------------------------------------------------------ graphs, tuning
+    def graph_begin(self):
+        self._check(self.L.chem_graph_begin(self.h), "chem_graph_begin")
+
+    def graph_end(self):
+        g = C.c_void_p()
+        self._check(self.L.chem_graph_end(self.h, C.byref(g)), "chem_graph_end")
+        return Graph(self, g)
+
+    def autotune(self, T, p, Y, dt, flags=None, ref_index=None):
+        """chem_autotune; returns [(schedule, queue_chunk, slots_per_cu, ms)] and
+        leaves the fastest configuration in the context's options."""
+        res = (TuneEntry * 16)()
+        cnt = C.c_int32(0)
+        self._check(self.L.chem_autotune(self.h, T.shape[0], _ptr(T), _ptr(p), _ptr(Y), float(dt),
+                                         _ptr(flags), _ptr(ref_index), res, 16, C.byref(cnt)),
+                    "chem_autotune")
+        return [(r.schedule, r.queue_chunk, r.slots_per_cu, r.ms) for r in res[:cnt.value]]
+
+
+class Graph:
+    """A recorded sequence of libchem calls (chem_graph)."""
+
+    def __init__(self, chem, handle):
+        self.chem, self.h = chem, handle
+
+    def launch(self):
+        self.chem._check(self.chem.L.chem_graph_launch(self.chem.h, self.h), "chem_graph_launch")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.chem.L.chem_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -12,6 +12,7 @@
 
 #include "../../include/chem.h"
 #include "mech_dev.hpp"
+#include "surrogate.hpp"
 
 namespace chem {
 int pick_np(int n);
@@ -65,8 +66,13 @@ struct chem_ctx {
     unsigned long long *d_reftmp = nullptr;
     double *d_snap = nullptr, *d_delta = nullptr;
     unsigned long long *h_stats = nullptr;   // pinned
-    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr, ev4 = nullptr,
+               ev5 = nullptr;
+    int64_t *d_refnone = nullptr;            // device -1: "no reference cell"
     int occ = 0;
+    bool in_capture = false, capture_failed = false;   // chem_graph_begin .. _end
+    Surrogate *sur = nullptr;                // learned surrogate (null: not available)
+    std::string sur_why;                     // why it is not available
 };
 
 static int fail(chem_ctx *c, int code, const char *fmt, ...) {
@@ -76,6 +82,7 @@ static int fail(chem_ctx *c, int code, const char *fmt, ...) {
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
     if (c) c->err = buf;
+    if (c && c->in_capture) c->capture_failed = true;   // the recording misses this call
     if (getenv("CHEM_LOG")) fprintf(stderr, "[libchem] %s\n", buf);
     return code;
 }
@@ -126,7 +133,14 @@ int chem_create(chem_ctx **out, int hip_device, void *hip_stream) {
         hipMalloc((void **)&c->d_small, 80 * sizeof(int)) != hipSuccess ||
         hipMalloc((void **)&c->d_reftmp, sizeof(unsigned long long)) != hipSuccess ||
         hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
-        hipEventCreate(&c->ev2) != hipSuccess || hipEventCreate(&c->ev3) != hipSuccess) {
+        hipEventCreate(&c->ev2) != hipSuccess || hipEventCreate(&c->ev3) != hipSuccess ||
+        hipEventCreate(&c->ev4) != hipSuccess || hipEventCreate(&c->ev5) != hipSuccess ||
+        hipMalloc((void **)&c->d_refnone, sizeof(int64_t)) != hipSuccess) {
+        chem_destroy(c);
+        return CHEM_E_HIP;
+    }
+    const int64_t none = -1;
+    if (hipMemcpy(c->d_refnone, &none, sizeof none, hipMemcpyHostToDevice) != hipSuccess) {
         chem_destroy(c);
         return CHEM_E_HIP;
     }
@@ -142,6 +156,9 @@ static void free_mech(chem_ctx *c) {
     if (c->d_delta) (void)hipFree(c->d_delta);
     c->d_mapw = c->d_snap = c->d_delta = nullptr;
     c->d_mech = nullptr;
+    delete c->sur;
+    c->sur = nullptr;
+    c->sur_why = "no mechanism";
     c->map_yf.clear();
     c->map_yo.clear();
     c->has_mech = false;
@@ -162,6 +179,9 @@ void chem_destroy(chem_ctx *c) {
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->ev2) (void)hipEventDestroy(c->ev2);
     if (c->ev3) (void)hipEventDestroy(c->ev3);
+    if (c->ev4) (void)hipEventDestroy(c->ev4);
+    if (c->ev5) (void)hipEventDestroy(c->ev5);
+    if (c->d_refnone) (void)hipFree(c->d_refnone);
     delete c;
 }
 
@@ -198,6 +218,64 @@ static int upload(chem_ctx *c, const std::vector<T> &h, const T **dptr) {
     if (!h.empty() && hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
         return fail(c, CHEM_E_HIP, "hipMemcpy mechanism");
     *dptr = (const T *)d;
+    return CHEM_OK;
+}
+
+// Element-conservation projection data of the surrogate: E_ek = a_ek / W_k and
+// (E E^T)^-1 by Gauss-Jordan elimination with partial pivoting.
+static int setup_surrogate(chem_ctx *c) {
+    const int E = c->E, N = c->N;
+    if (N > S_MAX_SPECIES) {
+        c->sur_why = "the surrogate takes at most 61 species";
+        return CHEM_OK;
+    }
+    if (E > 8) {
+        c->sur_why = "the surrogate takes at most 8 elements";
+        return CHEM_OK;
+    }
+    std::vector<double> Em((size_t)E * N), G((size_t)E * E, 0.0), Gi((size_t)E * E, 0.0);
+    for (int e = 0; e < E; ++e)
+        for (int k = 0; k < N; ++k) Em[(size_t)e * N + k] = (double)c->comp[k * E + e] / c->W[k];
+    for (int a = 0; a < E; ++a)
+        for (int b = 0; b < E; ++b) {
+            double t = 0.0;
+            for (int k = 0; k < N; ++k) t += Em[(size_t)a * N + k] * Em[(size_t)b * N + k];
+            G[a * E + b] = t;
+        }
+    for (int a = 0; a < E; ++a) Gi[a * E + a] = 1.0;
+    double gmax = 0.0;
+    for (double v : G) gmax = std::max(gmax, fabs(v));
+    for (int col = 0; col < E; ++col) {
+        int pr = col;
+        for (int r = col + 1; r < E; ++r)
+            if (fabs(G[r * E + col]) > fabs(G[pr * E + col])) pr = r;
+        if (!(fabs(G[pr * E + col]) > 1e-12 * gmax)) {
+            c->sur_why = "element matrix is singular (an element appears in no species)";
+            return CHEM_OK;
+        }
+        for (int q = 0; q < E; ++q) {
+            std::swap(G[col * E + q], G[pr * E + q]);
+            std::swap(Gi[col * E + q], Gi[pr * E + q]);
+        }
+        const double d = G[col * E + col];
+        for (int q = 0; q < E; ++q) { G[col * E + q] /= d; Gi[col * E + q] /= d; }
+        for (int r = 0; r < E; ++r) {
+            if (r == col) continue;
+            const double f = G[r * E + col];
+            for (int q = 0; q < E; ++q) {
+                G[r * E + q] -= f * G[col * E + q];
+                Gi[r * E + q] -= f * Gi[col * E + q];
+            }
+        }
+    }
+    Surrogate *sp = new Surrogate();
+    char err[256] = {0};
+    if (sp->init(N, E, Em, Gi, err)) {
+        delete sp;
+        return fail(c, CHEM_E_OOM, "surrogate: %s", err);
+    }
+    c->sur = sp;
+    c->sur_why.clear();
     return CHEM_OK;
 }
 
@@ -370,6 +448,7 @@ int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
     c->NP = pick_np(M.n);
     c->occ = 0;
     if (c->NP > 0 && (size_t)M.lds_doubles * 8 <= 160 * 1024) c->occ = queue_occupancy(c->NP, M);
+    if ((rc = setup_surrogate(c))) { free_mech(c); return rc; }
     c->has_mech = true;
     return CHEM_OK;
 }
@@ -469,14 +548,12 @@ static int check_integrator(chem_ctx *c) {
     return CHEM_OK;
 }
 
-int chem_integrate(chem_ctx *c, int64_t n, double *T, const double *p, double *Y, double dt,
-                   const uint8_t *flags, const int64_t *ref_index, double *h, uint32_t *cost,
-                   uint8_t *status, int32_t *steps, chem_stats *stats) {
-    if (!c) return CHEM_E_INVALID_ARG;
-    if (n < 0 || n > (int64_t)INT32_MAX || !(dt > 0.0) || !isfinite(dt))
-        return fail(c, CHEM_E_INVALID_ARG, "chem_integrate: bad n or dt");
-    if (n > 0 && (!T || !p || !Y)) return fail(c, CHEM_E_INVALID_ARG, "null state array");
-    if (flags && !ref_index) return fail(c, CHEM_E_INVALID_ARG, "flags need ref_index");
+// One call of the hot path: optional surrogate pass over flag-0 cells, work
+// queue, Rosenbrock integration of the remaining cells, mapped-cell scatter.
+static int integrate_core(chem_ctx *c, int64_t n, double *T, const double *p, double *Y, double dt,
+                          uint8_t *flags, const int64_t *ref_index, double *h, uint32_t *cost,
+                          uint8_t *status, int32_t *steps, chem_stats *stats,
+                          const chem_gate_params *gate) {
     int rc = check_integrator(c);
     if (rc) return rc;
     HIPCHK(c, hipSetDevice(c->device));
@@ -485,11 +562,28 @@ int chem_integrate(chem_ctx *c, int64_t n, double *T, const double *p, double *Y
     if (c->opt.schedule == CHEM_SCHED_QUEUE && n > c->cap) {
         if ((rc = chem_reserve(c, n))) return rc;
     }
+    if (gate && n > 0) {
+        if (!c->sur || !c->sur->trained)
+            return fail(c, CHEM_E_INVALID_ARG, "surrogate not available: %s",
+                        c->sur ? "no parameters (train or load first)" : c->sur_why.c_str());
+        if (c->sur->ws_rows < (int)std::min<int64_t>(n, 262144) && cap)
+            return fail(c, CHEM_E_CAPTURE_UNSAFE, "surrogate workspace growth during capture");
+    }
+    if (!ref_index) ref_index = c->d_refnone;
     hipStream_t s = c->stream;
     if (stats) HIPCHK(c, hipEventRecord(c->ev0, s));
     int *hist = c->d_small, *cursor = c->d_small + 32, *seg = c->d_small + 64, *nact = c->d_small + 72;
     HIPCHK(c, launch_queue_reset(hist, cursor, seg, nact, c->d_stats, s));
     if (n > 0) {
+        if (gate) {
+            if (stats) HIPCHK(c, hipEventRecord(c->ev4, s));
+            FeatSrc f{T, p, Y, nullptr, dt, n, c->N};
+            PostIn pin{c->M.nasa_t, c->M.invW, gate->tau_T, gate->y_min, gate->margin};
+            char err[256] = {0};
+            if (c->sur->apply(f, T, Y, flags, pin, c->d_stats, s, err))
+                return fail(c, CHEM_E_HIP, "surrogate: %s", err);
+            if (stats) HIPCHK(c, hipEventRecord(c->ev5, s));
+        }
         if (flags) HIPCHK(c, launch_ref_snapshot(n, c->N, T, Y, ref_index, c->d_snap, s));
         IntParams P{};
         P.rtol = c->opt.rtol;
@@ -525,9 +619,10 @@ int chem_integrate(chem_ctx *c, int64_t n, double *T, const double *p, double *Y
     HIPCHK(c, hipMemcpyAsync(c->h_stats, c->d_stats, 8 * sizeof(unsigned long long),
                              hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
-    float ms = 0.0f, msi = 0.0f;
+    float ms = 0.0f, msi = 0.0f, mss = 0.0f;
     HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
     if (n > 0) HIPCHK(c, hipEventElapsedTime(&msi, c->ev2, c->ev3));
+    if (n > 0 && gate) HIPCHK(c, hipEventElapsedTime(&mss, c->ev4, c->ev5));
     stats->cells_integrated = (int64_t)c->h_stats[0];
     stats->steps_accepted = (int64_t)c->h_stats[1];
     stats->steps_rejected = (int64_t)c->h_stats[2];
@@ -537,7 +632,178 @@ int chem_integrate(chem_ctx *c, int64_t n, double *T, const double *p, double *Y
     stats->reserved = 0;
     stats->ms_total = ms;
     stats->ms_integrate = msi;
+    stats->cells_surrogate = (int64_t)c->h_stats[6];
+    stats->cells_rejected = (int64_t)c->h_stats[7];
+    stats->ms_surrogate = mss;
     return (int)std::min<int64_t>(stats->cells_failed, INT32_MAX);
+}
+
+int chem_integrate(chem_ctx *c, int64_t n, double *T, const double *p, double *Y, double dt,
+                   const uint8_t *flags, const int64_t *ref_index, double *h, uint32_t *cost,
+                   uint8_t *status, int32_t *steps, chem_stats *stats) {
+    if (!c) return CHEM_E_INVALID_ARG;
+    if (n < 0 || n > (int64_t)INT32_MAX || !(dt > 0.0) || !isfinite(dt))
+        return fail(c, CHEM_E_INVALID_ARG, "chem_integrate: bad n or dt");
+    if (n > 0 && (!T || !p || !Y)) return fail(c, CHEM_E_INVALID_ARG, "null state array");
+    if (flags && !ref_index) return fail(c, CHEM_E_INVALID_ARG, "flags need ref_index");
+    return integrate_core(c, n, T, p, Y, dt, const_cast<uint8_t *>(flags), ref_index, h, cost, status,
+                          steps, stats, nullptr);
+}
+
+int chem_integrate_surrogate(chem_ctx *c, int64_t n, double *T, const double *p, double *Y,
+                             double dt, uint8_t *flags, const int64_t *ref_index,
+                             const chem_gate_params *gate, double *h, uint32_t *cost,
+                             uint8_t *status, int32_t *steps, chem_stats *stats) {
+    if (!c) return CHEM_E_INVALID_ARG;
+    if (n < 0 || n > (int64_t)INT32_MAX || !(dt > 0.0) || !isfinite(dt) || !gate)
+        return fail(c, CHEM_E_INVALID_ARG, "chem_integrate_surrogate: bad n, dt or gate");
+    if (n > 0 && (!T || !p || !Y || !flags)) return fail(c, CHEM_E_INVALID_ARG, "null state or flags array");
+    if (!(gate->tau_T >= 0.0) || !(gate->margin >= 0.0) || gate->y_min != gate->y_min)
+        return fail(c, CHEM_E_INVALID_ARG, "bad gate parameters");
+    return integrate_core(c, n, T, p, Y, dt, flags, ref_index, h, cost, status, steps, stats, gate);
+}
+
+// ------------------------------------------------------------ surrogate ----
+void chem_default_train_params(chem_train_params *t) {
+    t->epochs = 8;
+    t->batch = 4096;
+    t->lr_max = 2e-3;
+    t->lr_min = 2e-5;
+    t->seed = 0;
+    t->verbose = 0;
+}
+
+void chem_default_gate_params(chem_gate_params *g) {
+    g->tau_T = 0.5;
+    g->y_min = -1e-10;
+    g->margin = 0.0;
+}
+
+int64_t chem_surrogate_param_count(void) { return surrogate_param_count(); }
+
+static int check_surrogate(chem_ctx *c, bool need_trained) {
+    if (!c->has_mech) return fail(c, CHEM_E_NO_MECHANISM, "no mechanism");
+    if (!c->sur) return fail(c, CHEM_E_UNIMPL, "surrogate not available: %s", c->sur_why.c_str());
+    if (need_trained && !c->sur->trained)
+        return fail(c, CHEM_E_INVALID_ARG, "surrogate has no parameters (train or load first)");
+    return CHEM_OK;
+}
+
+int chem_surrogate_train(chem_ctx *c, int64_t n, const double *T0, const double *p, const double *Y0,
+                         const double *dt, const double *T1, const double *Y1,
+                         const chem_train_params *tp, float *loss_history) {
+    if (!c || !tp) return CHEM_E_INVALID_ARG;
+    int rc = check_surrogate(c, false);
+    if (rc) return rc;
+    if (n < 1 || n > (int64_t)INT32_MAX || !T0 || !p || !Y0 || !dt || !T1 || !Y1 || tp->epochs < 1 ||
+        tp->batch < 64 || tp->batch % 64 != 0 || tp->batch > 65536 || n < tp->batch ||
+        !(tp->lr_max > 0.0) || !(tp->lr_min >= 0.0))
+        return fail(c, CHEM_E_INVALID_ARG, "chem_surrogate_train: bad arguments");
+    if (capturing(c)) return fail(c, CHEM_E_CAPTURE_UNSAFE, "training during capture");
+    HIPCHK(c, hipSetDevice(c->device));
+    FeatSrc f{T0, p, Y0, dt, 0.0, n, c->N};
+    TgtSrc t{T0, Y0, T1, Y1, n, c->N};
+    char err[256] = {0};
+    if ((rc = c->sur->train(f, t, tp->epochs, tp->batch, tp->lr_max, tp->lr_min, tp->seed, loss_history,
+                            tp->verbose, c->stream, err)))
+        return fail(c, rc, "surrogate training: %s", err);
+    return CHEM_OK;
+}
+
+int chem_surrogate_get_params(chem_ctx *c, float *host) {
+    if (!c || !host) return CHEM_E_INVALID_ARG;
+    int rc = check_surrogate(c, true);
+    if (rc) return rc;
+    HIPCHK(c, hipSetDevice(c->device));
+    char err[256] = {0};
+    if (c->sur->get_params(host, c->stream, err)) return fail(c, CHEM_E_HIP, "%s", err);
+    return CHEM_OK;
+}
+
+int chem_surrogate_set_params(chem_ctx *c, const float *host) {
+    if (!c || !host) return CHEM_E_INVALID_ARG;
+    int rc = check_surrogate(c, false);
+    if (rc) return rc;
+    const int64_t np = surrogate_param_count();
+    for (int64_t i = 0; i < np; ++i)
+        if (!isfinite(host[i])) return fail(c, CHEM_E_INVALID_ARG, "non-finite parameter %lld", (long long)i);
+    for (int q = 0; q < S_IN; ++q)
+        if (!(host[np - 5 * S_IN + q] > 0.0f) || !(host[np - 3 * S_IN + q] > 0.0f))
+            return fail(c, CHEM_E_INVALID_ARG, "normalisation scales must be positive");
+    HIPCHK(c, hipSetDevice(c->device));
+    char err[256] = {0};
+    if (c->sur->set_params(host, c->stream, err)) return fail(c, CHEM_E_HIP, "%s", err);
+    return CHEM_OK;
+}
+
+static const char kSurMagic[8] = {'L', 'C', 'H', 'S', 'U', 'R', '0', '1'};
+
+int chem_surrogate_save(chem_ctx *c, const char *path) {
+    if (!c || !path) return CHEM_E_INVALID_ARG;
+    const int64_t np = surrogate_param_count();
+    std::vector<float> buf(np);
+    int rc = chem_surrogate_get_params(c, buf.data());
+    if (rc) return rc;
+    FILE *fp = fopen(path, "wb");
+    if (!fp) return fail(c, CHEM_E_INVALID_ARG, "cannot open %s", path);
+    const int32_t hdr[2] = {c->N, c->E};
+    bool ok = fwrite(kSurMagic, 1, 8, fp) == 8 && fwrite(hdr, sizeof hdr, 1, fp) == 1 &&
+              fwrite(&np, sizeof np, 1, fp) == 1 && fwrite(buf.data(), sizeof(float), np, fp) == (size_t)np;
+    ok = (fclose(fp) == 0) && ok;
+    return ok ? CHEM_OK : fail(c, CHEM_E_INVALID_ARG, "write error on %s", path);
+}
+
+int chem_surrogate_load(chem_ctx *c, const char *path) {
+    if (!c || !path) return CHEM_E_INVALID_ARG;
+    int rc = check_surrogate(c, false);
+    if (rc) return rc;
+    FILE *fp = fopen(path, "rb");
+    if (!fp) return fail(c, CHEM_E_INVALID_ARG, "cannot open %s", path);
+    char magic[8];
+    int32_t hdr[2];
+    int64_t np = 0;
+    const int64_t want = surrogate_param_count();
+    std::vector<float> buf(want);
+    bool ok = fread(magic, 1, 8, fp) == 8 && memcmp(magic, kSurMagic, 8) == 0 &&
+              fread(hdr, sizeof hdr, 1, fp) == 1 && fread(&np, sizeof np, 1, fp) == 1 && np == want &&
+              hdr[0] == c->N && hdr[1] == c->E &&
+              fread(buf.data(), sizeof(float), want, fp) == (size_t)want;
+    fclose(fp);
+    if (!ok) return fail(c, CHEM_E_INVALID_ARG, "%s: not a surrogate file for this mechanism", path);
+    return chem_surrogate_set_params(c, buf.data());
+}
+
+int chem_surrogate_forward(chem_ctx *c, int64_t n, const double *T, const double *p, const double *Y,
+                           const double *dt, float *out) {
+    if (!c) return CHEM_E_INVALID_ARG;
+    int rc = check_surrogate(c, true);
+    if (rc) return rc;
+    if (n < 0 || n > (int64_t)INT32_MAX || (n > 0 && (!T || !p || !Y || !dt || !out)))
+        return fail(c, CHEM_E_INVALID_ARG, "chem_surrogate_forward: bad arguments");
+    if (n == 0) return CHEM_OK;
+    if (capturing(c)) return fail(c, CHEM_E_CAPTURE_UNSAFE, "surrogate forward during capture");
+    HIPCHK(c, hipSetDevice(c->device));
+    FeatSrc f{T, p, Y, dt, 0.0, n, c->N};
+    char err[256] = {0};
+    if (c->sur->forward_rows(f, out, c->stream, err)) return fail(c, CHEM_E_HIP, "%s", err);
+    return CHEM_OK;
+}
+
+int chem_surrogate_loss_grad(chem_ctx *c, int64_t n, const double *T0, const double *p,
+                             const double *Y0, const double *dt, const double *T1, const double *Y1,
+                             float *grad, double *loss) {
+    if (!c) return CHEM_E_INVALID_ARG;
+    int rc = check_surrogate(c, true);
+    if (rc) return rc;
+    if (n < 64 || n > 65536 || n % 64 != 0 || !T0 || !p || !Y0 || !dt || !T1 || !Y1 || !grad || !loss)
+        return fail(c, CHEM_E_INVALID_ARG, "chem_surrogate_loss_grad: bad arguments");
+    if (capturing(c)) return fail(c, CHEM_E_CAPTURE_UNSAFE, "loss gradient during capture");
+    HIPCHK(c, hipSetDevice(c->device));
+    FeatSrc f{T0, p, Y0, dt, 0.0, n, c->N};
+    TgtSrc t{T0, Y0, T1, Y1, n, c->N};
+    char err[256] = {0};
+    if (c->sur->loss_grad(f, t, grad, loss, c->stream, err)) return fail(c, CHEM_E_HIP, "%s", err);
+    return CHEM_OK;
 }
 
 int chem_eval_rhs_jac(chem_ctx *c, int64_t n, const double *T, const double *p, const double *Y,
@@ -570,3 +836,138 @@ int chem_rodas_step(chem_ctx *c, int64_t n, const double *T, const double *p, co
     return CHEM_OK;
 }
 
+
+// ---------------------------------------------------------- graphs ---------
+struct chem_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+int chem_graph_begin(chem_ctx *c) {
+    if (!c) return CHEM_E_INVALID_ARG;
+    if (!c->stream) return fail(c, CHEM_E_INVALID_ARG, "capture needs a created stream, not the null stream");
+    if (capturing(c)) return fail(c, CHEM_E_CAPTURE_UNSAFE, "stream is already capturing");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    c->in_capture = true;
+    c->capture_failed = false;
+    return CHEM_OK;
+}
+
+int chem_graph_end(chem_ctx *c, chem_graph **out) {
+    if (!c || !out) return CHEM_E_INVALID_ARG;
+    *out = nullptr;
+    if (!capturing(c)) return fail(c, CHEM_E_INVALID_ARG, "stream is not capturing");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    const bool broken = c->capture_failed;
+    c->in_capture = c->capture_failed = false;
+    if (e != hipSuccess || !g || broken) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(c, CHEM_E_CAPTURE_UNSAFE, "capture invalid: %s",
+                    broken ? "a recorded call failed" : hipGetErrorString(e));
+    }
+    chem_graph *cg = new chem_graph();
+    cg->graph = g;
+    e = hipGraphInstantiate(&cg->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        chem_graph_destroy(cg);
+        return fail(c, CHEM_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    *out = cg;
+    return CHEM_OK;
+}
+
+int chem_graph_launch(chem_ctx *c, const chem_graph *g) {
+    if (!c || !g || !g->exec) return CHEM_E_INVALID_ARG;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipGraphLaunch(g->exec, c->stream));
+    return CHEM_OK;
+}
+
+void chem_graph_destroy(chem_graph *g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
+// ---------------------------------------------------------- autotune -------
+int chem_autotune(chem_ctx *c, int64_t n, const double *T, const double *p, const double *Y,
+                  double dt, const uint8_t *flags, const int64_t *ref_index, chem_tune_entry *res,
+                  int32_t max_res, int32_t *n_res) {
+    if (!c) return CHEM_E_INVALID_ARG;
+    if (n < 1 || n > (int64_t)INT32_MAX || !T || !p || !Y || !(dt > 0.0) || !isfinite(dt) ||
+        (flags && !ref_index) || max_res < 0 || (max_res > 0 && !res))
+        return fail(c, CHEM_E_INVALID_ARG, "chem_autotune: bad arguments");
+    int rc = check_integrator(c);
+    if (rc) return rc;
+    if (capturing(c)) return fail(c, CHEM_E_CAPTURE_UNSAFE, "autotune during capture");
+    HIPCHK(c, hipSetDevice(c->device));
+    if ((rc = chem_reserve(c, n))) return rc;
+    const size_t nY = (size_t)c->N * n;
+    double *dT = nullptr, *dY = nullptr, *dh = nullptr;
+    uint32_t *dcost = nullptr, *dcost0 = nullptr;
+    auto release = [&]() {
+        (void)hipStreamSynchronize(c->stream);
+        for (void *q : {(void *)dT, (void *)dY, (void *)dh, (void *)dcost, (void *)dcost0})
+            if (q) (void)hipFree(q);
+    };
+    if (hipMalloc((void **)&dT, sizeof(double) * n) != hipSuccess ||
+        hipMalloc((void **)&dY, sizeof(double) * nY) != hipSuccess ||
+        hipMalloc((void **)&dh, sizeof(double) * n) != hipSuccess ||
+        hipMalloc((void **)&dcost, sizeof(uint32_t) * n) != hipSuccess ||
+        hipMalloc((void **)&dcost0, sizeof(uint32_t) * n) != hipSuccess) {
+        release();
+        return fail(c, CHEM_E_OOM, "chem_autotune: scratch for %lld cells", (long long)n);
+    }
+    hipStream_t s = c->stream;
+    auto fresh = [&](const uint32_t *cost_src) -> hipError_t {
+        hipError_t e;
+        if ((e = hipMemcpyAsync(dT, T, sizeof(double) * n, hipMemcpyDeviceToDevice, s))) return e;
+        if ((e = hipMemcpyAsync(dY, Y, sizeof(double) * nY, hipMemcpyDeviceToDevice, s))) return e;
+        if ((e = hipMemsetAsync(dh, 0, sizeof(double) * n, s))) return e;
+        if (cost_src) return hipMemcpyAsync(dcost, cost_src, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s);
+        return hipMemsetAsync(dcost, 0, sizeof(uint32_t) * n, s);
+    };
+    const chem_options saved = c->opt;
+    uint8_t *fl = const_cast<uint8_t *>(flags);
+    chem_stats st{};
+    // one untimed pass records the per-cell cost that orders the queue
+    hipError_t e = fresh(nullptr);
+    if (e != hipSuccess) { release(); return fail(c, CHEM_E_HIP, "autotune copy: %s", hipGetErrorString(e)); }
+    rc = integrate_core(c, n, dT, p, dY, dt, fl, ref_index, dh, dcost, nullptr, nullptr, &st, nullptr);
+    if (rc < 0) { release(); return rc; }
+    e = hipMemcpyAsync(dcost0, dcost, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) { release(); return fail(c, CHEM_E_HIP, "autotune copy: %s", hipGetErrorString(e)); }
+    struct Cand { int sched, chunk, slots; };
+    std::vector<Cand> cands;
+    const int occ = std::max(1, c->occ);
+    cands.push_back({CHEM_SCHED_PLAIN, 0, 0});
+    for (int slots : {std::max(1, occ / 2), occ})
+        for (int chunk : {1, 2, 4, 8}) cands.push_back({CHEM_SCHED_QUEUE, chunk, slots});
+    double best = INFINITY;
+    chem_options best_opt = saved;
+    int k = 0;
+    for (const Cand &cd : cands) {
+        c->opt = saved;
+        c->opt.schedule = cd.sched;
+        c->opt.queue_chunk = cd.chunk;
+        c->opt.slots_per_cu = cd.slots;
+        if ((e = fresh(dcost0)) != hipSuccess) {
+            c->opt = saved;
+            release();
+            return fail(c, CHEM_E_HIP, "autotune copy: %s", hipGetErrorString(e));
+        }
+        rc = integrate_core(c, n, dT, p, dY, dt, fl, ref_index, dh, dcost, nullptr, nullptr, &st, nullptr);
+        if (rc < 0) { c->opt = saved; release(); return rc; }
+        if (k < max_res) res[k] = chem_tune_entry{cd.sched, cd.chunk, cd.slots, st.ms_total};
+        ++k;
+        if (st.ms_total < best) { best = st.ms_total; best_opt = c->opt; }
+    }
+    c->opt = best_opt;
+    if (n_res) *n_res = std::min(k, max_res);
+    release();
+    return CHEM_OK;
+}

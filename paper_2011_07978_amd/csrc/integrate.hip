@@ -473,7 +473,7 @@ __global__ __launch_bounds__(64) void k_integrate_plain(const MechDev *__restric
     extern __shared__ double lds[];
     init_sentinels(M, lds);
     const int64_t cell = blockIdx.x;
-    if (P.flags && P.flags[cell] == 2) return;
+    if (P.flags && P.flags[cell] >= 2) return;
     integrate_cell<NP>(M, P, cell, lds);
 }
 

@@ -125,6 +125,8 @@ __global__ __launch_bounds__(MAP_BLOCK) void k_map_scatter(
         }
         T[i] = Tn;
         if (status) status[i] = 5;
+    } else if (i < ncells && status && flags[i] == 3) {
+        status[i] = 6;   // advanced by the surrogate before integration
     }
     const unsigned long long cnt = __ballot(mapped);
     if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(&stats[5], (unsigned long long)__popcll(cnt));
@@ -132,7 +134,7 @@ __global__ __launch_bounds__(MAP_BLOCK) void k_map_scatter(
 
 // ------------------------------------------------------------------ queue ---
 // Heavy-first order: bucket = 31 - floor(log2(cost + 1)), so the most expensive
-// cells of the previous call come first; cells flagged 2 (mapped) are skipped.
+// cells of the previous call come first; cells flagged 2 (mapped) or 3 (surrogate) are skipped.
 __device__ __forceinline__ int cost_bucket(const uint32_t *cost, int64_t i) {
     if (!cost) return NBUCKET - 1;
     uint32_t c = cost[i];
@@ -156,7 +158,7 @@ __global__ __launch_bounds__(MAP_BLOCK) void k_queue_count(int64_t ncells, const
     if (threadIdx.x < NBUCKET) sh[threadIdx.x] = 0;
     __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * MAP_BLOCK + threadIdx.x;
-    if (i < ncells && !(flags && flags[i] == 2)) atomicAdd(&sh[cost_bucket(cost, i)], 1);
+    if (i < ncells && !(flags && flags[i] >= 2)) atomicAdd(&sh[cost_bucket(cost, i)], 1);
     __syncthreads();
     if (threadIdx.x < NBUCKET && sh[threadIdx.x]) atomicAdd(&hist[threadIdx.x], sh[threadIdx.x]);
 }
@@ -178,7 +180,7 @@ __global__ __launch_bounds__(MAP_BLOCK) void k_queue_scatter(int64_t ncells, con
                                                              const int *offsets, int *cursor,
                                                              int *queue) {
     const int64_t i = (int64_t)blockIdx.x * MAP_BLOCK + threadIdx.x;
-    if (i >= ncells || (flags && flags[i] == 2)) return;
+    if (i >= ncells || (flags && flags[i] >= 2)) return;
     const int b = cost_bucket(cost, i);
     const int pos = offsets[b] + atomicAdd(&cursor[b], 1);
     queue[pos] = (int)i;

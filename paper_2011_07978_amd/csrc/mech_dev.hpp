@@ -61,7 +61,7 @@ struct IntParams {
     uint32_t *cost;         // nullable
     uint8_t *status;        // nullable
     int32_t *steps;         // nullable [2*ncells]
-    const uint8_t *flags;   // nullable (plain schedule skips flag 2)
+    const uint8_t *flags;   // nullable (plain schedule skips flags 2 and 3)
     // queue schedule
     const int *queue;       // sorted active cells
     int *seg_ctr;           // [NSEG] consumed items per segment

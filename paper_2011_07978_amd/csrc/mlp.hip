@@ -1,0 +1,718 @@
+// Learned surrogate for the per-cell dt-advance: BF16-MFMA MLP training and
+// inference, element-conservation projection and acceptance gate.
+//
+// Network (shared definition with the oracle): features
+//   x = (ln T, ln p, Y_1..Y_N, ln dt), normalised and padded to 64,
+// four hidden layers of 256 with GELU (erf form), output 64 (first N+1 used:
+// normalised dY_1..dY_N, dT).  Weights and activations are bfloat16, products
+// accumulate in FP32 on the matrix cores (v_mfma_f32_16x16x32_bf16), biases and
+// GELU in FP32.  Training: mean-squared error on the normalised outputs, Adam
+// on FP32 master weights.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <numeric>
+#include <random>
+#include <vector>
+
+#include "mech_dev.hpp"
+#include "surrogate.hpp"
+
+namespace chem {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float x) {
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu)) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ float gelu_f(float z) {
+    return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+}
+__device__ __forceinline__ float gelu_df(float z) {
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
+           z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// ------------------------------------------------------------------ GEMM ----
+// C[m][n] = sum_k A[m][k] B[n][k]  (A: M x K, B: N x K, bf16, k contiguous).
+// Workgroup tile 64 x 64, four waves of 32 x 32, each 2 x 2 MFMA 16x16x32 blocks.
+// MFMA operand layout (gfx950, checked on hardware): lane l holds A row l%16,
+// k = 8(l/16)..+7; B column l%16, same k; D rows 4(l/16)+i, column l%16.
+enum { EPI_HID = 0, EPI_OUT = 1, EPI_PLAIN = 2, EPI_OUT_T = 3 };
+struct GemmEpi {
+    const float *bias;
+    uint16_t *H; int ldh;      // bf16 GELU output
+    uint16_t *HT; int ldht;    // bf16 GELU output, transposed (nullable)
+    float *Z; int ldz;         // f32 pre-activation (nullable)
+    float *C; int ldc;         // f32 output
+};
+
+template <int EPI>
+__global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t *__restrict__ A, int lda,
+                                                 const uint16_t *__restrict__ B, int ldb, int M,
+                                                 int N, int K, GemmEpi e) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int m0 = blockIdx.x * 64 + (w >> 1) * 32, n0 = blockIdx.y * 64 + (w & 1) * 32;
+    const int r16 = lane & 15, kq = (lane >> 4) * 8;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bf16x8 zero8 = {};
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        bf16x8 a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int row = m0 + 16 * i + r16;
+            a[i] = row < M ? *(const bf16x8 *)(A + (size_t)row * lda + k0 + kq) : zero8;
+            const int col = n0 + 16 * i + r16;
+            b[i] = col < N ? *(const bf16x8 *)(B + (size_t)col * ldb + k0 + kq) : zero8;
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + 16 * i + 4 * (lane >> 4) + r;
+                const int col = n0 + 16 * j + r16;
+                if (row >= M || col >= N) continue;
+                const float v = acc[i][j][r];
+                if (EPI == EPI_HID) {
+                    const float z = v + e.bias[col];
+                    const uint16_t g = f2bf(gelu_f(z));
+                    e.H[(size_t)row * e.ldh + col] = g;
+                    if (e.HT) e.HT[(size_t)col * e.ldht + row] = g;
+                    if (e.Z) e.Z[(size_t)row * e.ldz + col] = z;
+                } else if (EPI == EPI_OUT) {
+                    e.C[(size_t)row * e.ldc + col] = v + e.bias[col];
+                } else if (EPI == EPI_OUT_T) {
+                    e.C[(size_t)col * e.ldc + row] = v + e.bias[col];
+                } else {
+                    e.C[(size_t)row * e.ldc + col] = v;
+                }
+            }
+}
+
+template <int EPI>
+static void gemm(const uint16_t *A, int lda, const uint16_t *B, int ldb, int M, int N, int K,
+                 const GemmEpi &e, hipStream_t s) {
+    dim3 grid((M + 63) / 64, (N + 63) / 64);
+    hipLaunchKernelGGL(k_gemm_nt<EPI>, grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, e);
+}
+
+// ------------------------------------------------------------- features ----
+__device__ __forceinline__ double raw_feature(const FeatSrc &f, int64_t i, int c) {
+    if (c == 0) return log(f.T[i]);
+    if (c == 1) return log(f.p[i]);
+    if (c < f.N + 2) return f.Y[(int64_t)(c - 2) * f.n + i];
+    if (c == f.N + 2) return log(f.dt_scalar > 0.0 ? f.dt_scalar : f.dt[i]);
+    return 0.0;
+}
+
+// per-feature sum, sum of squares, min, max (FP64), one block per feature
+__global__ __launch_bounds__(256) void k_feature_moments(FeatSrc f, int ncol, double *out) {
+    const int c = blockIdx.x;
+    double s = 0.0, s2 = 0.0, mn = INFINITY, mx = -INFINITY;
+    for (int64_t i = threadIdx.x; i < f.n; i += blockDim.x) {
+        const double v = raw_feature(f, i, c);
+        s += v;
+        s2 += v * v;
+        mn = fmin(mn, v);
+        mx = fmax(mx, v);
+    }
+    __shared__ double sh[4][256];
+    sh[0][threadIdx.x] = s; sh[1][threadIdx.x] = s2; sh[2][threadIdx.x] = mn; sh[3][threadIdx.x] = mx;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + st];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + st];
+            sh[2][threadIdx.x] = fmin(sh[2][threadIdx.x], sh[2][threadIdx.x + st]);
+            sh[3][threadIdx.x] = fmax(sh[3][threadIdx.x], sh[3][threadIdx.x + st]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[4 * c] = sh[0][0]; out[4 * c + 1] = sh[1][0];
+        out[4 * c + 2] = sh[2][0]; out[4 * c + 3] = sh[3][0];
+    }
+}
+
+// targets: dY_k = Y1_k - Y0_k (k < N), dT = T1 - T0
+__device__ __forceinline__ double raw_target(const TgtSrc &t, int64_t i, int c) {
+    if (c < t.N) return t.Y1[(int64_t)c * t.n + i] - t.Y0[(int64_t)c * t.n + i];
+    return t.T1[i] - t.T0[i];
+}
+__global__ __launch_bounds__(256) void k_target_moments(TgtSrc t, double *out) {
+    const int c = blockIdx.x;
+    double s = 0.0, s2 = 0.0;
+    for (int64_t i = threadIdx.x; i < t.n; i += blockDim.x) {
+        const double v = raw_target(t, i, c);
+        s += v;
+        s2 += v * v;
+    }
+    __shared__ double sh[2][256];
+    sh[0][threadIdx.x] = s; sh[1][threadIdx.x] = s2;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + st];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { out[2 * c] = sh[0][0]; out[2 * c + 1] = sh[1][0]; }
+}
+
+// rows r < B of the batch from samples idx[r] (nullable: base + r):
+// X[r][c] bf16 normalised features, XT[c][r] its transpose (nullable),
+// Tg[r][c] normalised targets (nullable)
+__global__ __launch_bounds__(256) void k_build_rows(FeatSrc f, TgtSrc t, const int *idx, int64_t base,
+                                                    int B, const float *norm, uint16_t *X,
+                                                    uint16_t *XT, int ldxt, float *Tg) {
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int c = threadIdx.x & 63;
+    if (r >= B) return;
+    const int64_t i = idx ? (int64_t)idx[r] : base + r;
+    const int nfeat = f.N + 3;
+    uint16_t v = 0;
+    if (c < nfeat) v = f2bf((float)((raw_feature(f, i, c) - norm[c]) / norm[64 + c]));
+    X[(size_t)r * S_IN + c] = v;
+    if (XT) XT[(size_t)c * ldxt + r] = v;
+    if (Tg) {
+        float tv = 0.0f;
+        if (c < t.N + 1) tv = (float)((raw_target(t, i, c) - norm[128 + c]) / norm[192 + c]);
+        Tg[(size_t)r * S_OUT + c] = tv;
+    }
+}
+
+// ------------------------------------------------------------- backward ----
+// dO = 2 (out - target) / (B * nout) for the first nout columns, 0 elsewhere
+__global__ __launch_bounds__(256) void k_out_grad(const float *out, const float *Tg, int B, int nout,
+                                                  float *dOf, uint16_t *dZ, uint16_t *dZT, int ldt,
+                                                  double *loss) {
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int c = threadIdx.x & 63;
+    float g = 0.0f;
+    double l2 = 0.0;
+    if (r < B && c < nout) {
+        const float e = out[(size_t)r * S_OUT + c] - Tg[(size_t)r * S_OUT + c];
+        g = 2.0f * e / ((float)B * (float)nout);
+        l2 = (double)e * e;
+    }
+    if (r < B) {
+        dOf[(size_t)r * S_OUT + c] = g;
+        const uint16_t gb = f2bf(g);
+        dZ[(size_t)r * S_OUT + c] = gb;
+        dZT[(size_t)c * ldt + r] = gb;
+    }
+    for (int m = 32; m > 0; m >>= 1) l2 += __shfl_xor(l2, m);
+    if ((threadIdx.x & 63) == 0 && l2 != 0.0) atomicAdd(loss, l2);
+}
+
+// dZ = dH * GELU'(Z), as f32 (for the bias gradient) and bf16 (+ transpose)
+__global__ __launch_bounds__(256) void k_gelu_back(const float *dH, const float *Z, int B,
+                                                   float *dZf, uint16_t *dZ, uint16_t *dZT, int ldt) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (int64_t)B * S_HID) return;
+    const int r = (int)(t / S_HID), c = (int)(t % S_HID);
+    const float g = dH[t] * gelu_df(Z[t]);
+    dZf[t] = g;
+    const uint16_t gb = f2bf(g);
+    dZ[t] = gb;
+    dZT[(size_t)c * ldt + r] = gb;
+}
+
+// column sums of src [B x ncol] (bias gradients), one thread per column
+__global__ __launch_bounds__(256) void k_colsum(const float *src, int B, int ncol, float *dst) {
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= ncol) return;
+    float s = 0.0f;
+    for (int r = 0; r < B; ++r) s += src[(size_t)r * ncol + c];
+    dst[c] = s;
+}
+
+__global__ __launch_bounds__(256) void k_adam(float *P, const float *G, float *m, float *v, int64_t n,
+                                              float lr, float b1, float b2, float eps, float c1,
+                                              float c2) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float g = G[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * g;
+    const float vi = b2 * v[i] + (1.0f - b2) * g * g;
+    m[i] = mi;
+    v[i] = vi;
+    P[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// bf16 copies of a layer's weights: Wb [no x ni] and WbT [ni x no]
+__global__ __launch_bounds__(256) void k_refresh(const float *W, int no, int ni, uint16_t *Wb,
+                                                 uint16_t *WbT) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= no * ni) return;
+    const int o = t / ni, i = t % ni;
+    const uint16_t b = f2bf(W[t]);
+    Wb[t] = b;
+    WbT[(size_t)i * no + o] = b;
+}
+
+// ------------------------------------------------------ projection + gate ----
+struct PostParams {
+    int N, nel;
+    const double *E;       // [nel][N] a_ek / W_k
+    const double *Ginv;    // [nel][nel] (E E^T)^-1
+    const double *nasa_t;  // species thermo (a1..a7, a2/2, a3/3, a4/4, a5/5, ...)
+    const double *invW;
+    const float *norm;     // mu_x, sd_x, mu_o, sd_o, xmin, xmax
+    double tau_T, y_min, margin;
+};
+
+// One cell per thread.  outT [64][m] normalised network outputs of chunk
+// rows; row r is cell base + r.  Accepted cells get Y' = Y + P dY, T from
+// enthalpy conservation, flag 3; rejected cells are left untouched.
+__global__ __launch_bounds__(256) void k_surrogate_post(FeatSrc f, int64_t base, int m,
+                                                        const float *outT, PostParams q, double *T,
+                                                        double *Y, uint8_t *flags,
+                                                        unsigned long long *stats) {
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    bool accept = false, tried = false;
+    if (r < m) {
+        const int64_t i = base + r;
+        const int N = q.N;
+        if (!flags || flags[i] == 0) {
+            tried = true;
+            bool ok = true;
+            // out-of-distribution box on the raw features
+            for (int c = 0; c < N + 3 && ok; ++c) {
+                const double v = raw_feature(f, i, c);
+                const double lo = q.norm[256 + c], hi = q.norm[320 + c];
+                const double span = hi - lo;
+                ok = v >= lo - q.margin * span && v <= hi + q.margin * span;
+            }
+            double lam[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            double dT = 0.0, Tn = 0.0;
+            if (ok) {
+                double rr[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                for (int k = 0; k < N; ++k) {
+                    const double d = (double)outT[(size_t)k * m + r] * q.norm[192 + k] + q.norm[128 + k];
+                    for (int e = 0; e < q.nel; ++e) rr[e] += q.E[e * N + k] * d;
+                }
+                for (int a = 0; a < q.nel; ++a) {
+                    double s = 0.0;
+                    for (int b = 0; b < q.nel; ++b) s += q.Ginv[a * q.nel + b] * rr[b];
+                    lam[a] = s;
+                }
+                dT = (double)outT[(size_t)N * m + r] * q.norm[192 + N] + q.norm[128 + N];
+                // projected increments: positivity and the enthalpy polynomial
+                double Bo[6] = {0, 0, 0, 0, 0, 0}, Bn[6] = {0, 0, 0, 0, 0, 0};
+                for (int k = 0; k < N && ok; ++k) {
+                    double d = (double)outT[(size_t)k * m + r] * q.norm[192 + k] + q.norm[128 + k];
+                    for (int e = 0; e < q.nel; ++e) d -= q.E[e * N + k] * lam[e];
+                    const double yo = Y[(int64_t)k * f.n + i];
+                    const double yn = yo + d;
+                    ok = yn >= q.y_min;
+                    const double iw = q.invW[k];
+                    const double c6[6] = {q.nasa_t[k], q.nasa_t[7 * N + k], q.nasa_t[8 * N + k],
+                                          q.nasa_t[9 * N + k], q.nasa_t[10 * N + k], q.nasa_t[5 * N + k]};
+#pragma unroll
+                    for (int s = 0; s < 6; ++s) {
+                        Bo[s] += yo * iw * c6[s];
+                        Bn[s] += yn * iw * c6[s];
+                    }
+                }
+                if (ok) {
+                    const double T0 = T[i];
+                    const double h0 = Bo[5] + T0 * (Bo[0] + T0 * (Bo[1] + T0 * (Bo[2] + T0 * (Bo[3] + T0 * Bo[4]))));
+                    Tn = T0 + dT;
+                    for (int it = 0; it < 50; ++it) {
+                        const double F = Bn[5] + Tn * (Bn[0] + Tn * (Bn[1] + Tn * (Bn[2] + Tn * (Bn[3] + Tn * Bn[4])))) - h0;
+                        const double dF = Bn[0] + Tn * (2.0 * Bn[1] + Tn * (3.0 * Bn[2] + Tn * (4.0 * Bn[3] + Tn * 5.0 * Bn[4])));
+                        const double step = F / dF;
+                        Tn -= step;
+                        if (fabs(step) < 1e-10) break;
+                    }
+                    ok = fabs(T0 + dT - Tn) <= q.tau_T && Tn > 0.0;
+                }
+            }
+            if (ok) {
+                for (int k = 0; k < N; ++k) {
+                    double d = (double)outT[(size_t)k * m + r] * q.norm[192 + k] + q.norm[128 + k];
+                    for (int e = 0; e < q.nel; ++e) d -= q.E[e * N + k] * lam[e];
+                    Y[(int64_t)k * f.n + i] += d;
+                }
+                T[i] = Tn;
+                if (flags) flags[i] = 3;
+                accept = true;
+            }
+        }
+    }
+    const unsigned long long na = __ballot(accept), nt = __ballot(tried);
+    if ((threadIdx.x & 63) == 0) {
+        if (na) atomicAdd(&stats[6], (unsigned long long)__popcll(na));
+        if (nt & ~na) atomicAdd(&stats[7], (unsigned long long)__popcll(nt & ~na));
+    }
+}
+
+// ================================================================ host ======
+static int layer_in(int l) { return l == 0 ? S_IN : S_HID; }
+static int layer_out(int l) { return l == 4 ? S_OUT : S_HID; }
+
+int64_t surrogate_param_count() {
+    int64_t n = 0;
+    for (int l = 0; l < 5; ++l) n += (int64_t)layer_out(l) * layer_in(l) + layer_out(l);
+    return n + 6 * S_IN;
+}
+static int64_t weights_count() { return surrogate_param_count() - 6 * S_IN; }
+static int64_t layer_offset(int l) {
+    int64_t o = 0;
+    for (int q = 0; q < l; ++q) o += (int64_t)layer_out(q) * layer_in(q) + layer_out(q);
+    return o;
+}
+
+#define SCHK(x)                                                         \
+    do {                                                                \
+        hipError_t e_ = (x);                                            \
+        if (e_ != hipSuccess) {                                         \
+            snprintf(err, 256, "%s: %s", #x, hipGetErrorString(e_));    \
+            return -3;                                                  \
+        }                                                               \
+    } while (0)
+
+template <class T>
+static hipError_t dalloc(T **p, size_t count) {
+    return hipMalloc((void **)p, std::max<size_t>(1, count) * sizeof(T));
+}
+
+Surrogate::~Surrogate() {
+    for (void *p : bufs) (void)hipFree(p);
+    for (void *p : ws) (void)hipFree(p);
+}
+
+int Surrogate::init(int N_, int nel_, const std::vector<double> &E_host,
+                    const std::vector<double> &Ginv_host, char *err) {
+    N = N_;
+    nel = nel_;
+    const int64_t np = surrogate_param_count();
+    float *fp = nullptr;
+    SCHK(dalloc(&fp, np)); bufs.push_back(fp); P = fp;
+    SCHK(dalloc(&fp, np)); bufs.push_back(fp); G = fp;
+    SCHK(dalloc(&fp, np)); bufs.push_back(fp); mA = fp;
+    SCHK(dalloc(&fp, np)); bufs.push_back(fp); vA = fp;
+    for (int l = 0; l < 5; ++l) {
+        uint16_t *b = nullptr;
+        SCHK(dalloc(&b, (size_t)layer_out(l) * layer_in(l))); bufs.push_back(b); Wb[l] = b;
+        SCHK(dalloc(&b, (size_t)layer_out(l) * layer_in(l))); bufs.push_back(b); WbT[l] = b;
+    }
+    double *dp = nullptr;
+    SCHK(dalloc(&dp, E_host.size())); bufs.push_back(dp); E = dp;
+    SCHK(hipMemcpy(E, E_host.data(), sizeof(double) * E_host.size(), hipMemcpyHostToDevice));
+    SCHK(dalloc(&dp, Ginv_host.size())); bufs.push_back(dp); Ginv = dp;
+    SCHK(hipMemcpy(Ginv, Ginv_host.data(), sizeof(double) * Ginv_host.size(), hipMemcpyHostToDevice));
+    SCHK(dalloc(&dp, 1)); bufs.push_back(dp); d_loss = dp;
+    return 0;
+}
+
+int Surrogate::refresh(hipStream_t s, char *err) {
+    for (int l = 0; l < 5; ++l) {
+        const int no = layer_out(l), ni = layer_in(l);
+        hipLaunchKernelGGL(k_refresh, dim3((no * ni + 255) / 256), dim3(256), 0, s,
+                           P + layer_offset(l), no, ni, Wb[l], WbT[l]);
+    }
+    SCHK(hipGetLastError());
+    return 0;
+}
+
+int Surrogate::set_params(const float *host, hipStream_t s, char *err) {
+    SCHK(hipMemcpyAsync(P, host, sizeof(float) * surrogate_param_count(), hipMemcpyHostToDevice, s));
+    SCHK(hipStreamSynchronize(s));
+    int rc = refresh(s, err);
+    if (rc) return rc;
+    trained = true;
+    return 0;
+}
+
+int Surrogate::get_params(float *host, hipStream_t s, char *err) {
+    SCHK(hipMemcpyAsync(host, P, sizeof(float) * surrogate_param_count(), hipMemcpyDeviceToHost, s));
+    SCHK(hipStreamSynchronize(s));
+    return 0;
+}
+
+// workspace for up to B rows: activations, transposes, pre-activations
+int Surrogate::reserve_ws(int B, bool training, char *err) {
+    if (B <= ws_rows && (!training || ws_training)) return 0;
+    for (void *p : ws) (void)hipFree(p);
+    ws.clear();
+    auto get16 = [&](uint16_t **p, size_t n) { hipError_t e = dalloc(p, n); ws.push_back(*p); return e; };
+    auto get32 = [&](float **p, size_t n) { hipError_t e = dalloc(p, n); ws.push_back(*p); return e; };
+    SCHK(get16(&X, (size_t)B * S_IN));
+    for (int l = 0; l < 4; ++l) SCHK(get16(&H[l], (size_t)B * S_HID));
+    SCHK(get32(&out, (size_t)B * S_OUT));
+    if (training) {
+        SCHK(get16(&XT, (size_t)B * S_IN));
+        for (int l = 0; l < 4; ++l) {
+            SCHK(get16(&HT[l], (size_t)B * S_HID));
+            SCHK(get32(&Z[l], (size_t)B * S_HID));
+        }
+        SCHK(get32(&Tg, (size_t)B * S_OUT));
+        SCHK(get32(&dOf, (size_t)B * S_OUT));
+        SCHK(get16(&dZ5, (size_t)B * S_OUT));
+        SCHK(get16(&dZ5T, (size_t)B * S_OUT));
+        SCHK(get32(&dH, (size_t)B * S_HID));
+        SCHK(get32(&dZf, (size_t)B * S_HID));
+        SCHK(get16(&dZb, (size_t)B * S_HID));
+        SCHK(get16(&dZbT, (size_t)B * S_HID));
+    }
+    int *ip = nullptr;
+    SCHK(dalloc(&ip, (size_t)B)); ws.push_back(ip); idx = ip;
+    ws_rows = B;
+    ws_training = training;
+    return 0;
+}
+
+// forward of B rows already in X (inference epilogue unless training)
+void Surrogate::forward(int B, bool training, bool out_transposed, hipStream_t s) {
+    const uint16_t *in = X;
+    int ldin = S_IN;
+    for (int l = 0; l < 4; ++l) {
+        GemmEpi e{};
+        e.bias = P + layer_offset(l) + (int64_t)layer_out(l) * layer_in(l);
+        e.H = H[l]; e.ldh = S_HID;
+        if (training) { e.HT = HT[l]; e.ldht = B; e.Z = Z[l]; e.ldz = S_HID; }
+        gemm<EPI_HID>(in, ldin, Wb[l], layer_in(l), B, S_HID, layer_in(l), e, s);
+        in = H[l];
+        ldin = S_HID;
+    }
+    GemmEpi e{};
+    e.bias = P + layer_offset(4) + (int64_t)S_OUT * S_HID;
+    e.C = out;
+    if (out_transposed) {
+        e.ldc = B;
+        gemm<EPI_OUT_T>(in, S_HID, Wb[4], S_HID, B, S_OUT, S_HID, e, s);
+    } else {
+        e.ldc = S_OUT;
+        gemm<EPI_OUT>(in, S_HID, Wb[4], S_HID, B, S_OUT, S_HID, e, s);
+    }
+}
+
+// gradients of the mean-squared error for the B rows in X / Tg into G
+void Surrogate::backward(int B, hipStream_t s) {
+    const int nout = N + 1;
+    hipLaunchKernelGGL(k_out_grad, dim3((B + 3) / 4), dim3(256), 0, s, out, Tg, B, nout, dOf, dZ5,
+                       dZ5T, B, d_loss);
+    // output layer
+    {
+        GemmEpi e{};
+        e.C = G + layer_offset(4); e.ldc = S_HID;
+        gemm<EPI_PLAIN>(dZ5T, B, HT[3], B, S_OUT, S_HID, B, e, s);          // dW5 = dZ5^T H4
+        hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, s, dOf, B, S_OUT,
+                           G + layer_offset(4) + (int64_t)S_OUT * S_HID);
+        GemmEpi e2{};
+        e2.C = dH; e2.ldc = S_HID;
+        gemm<EPI_PLAIN>(dZ5, S_OUT, WbT[4], S_OUT, B, S_HID, S_OUT, e2, s);    // dH4 = dZ5 W5
+    }
+    for (int l = 3; l >= 0; --l) {
+        hipLaunchKernelGGL(k_gelu_back, dim3((B * S_HID + 255) / 256), dim3(256), 0, s, dH, Z[l], B,
+                           dZf, dZb, dZbT, B);
+        const int ni = layer_in(l);
+        GemmEpi e{};
+        e.C = G + layer_offset(l); e.ldc = ni;
+        const uint16_t *inT = l == 0 ? XT : HT[l - 1];
+        gemm<EPI_PLAIN>(dZbT, B, inT, B, S_HID, ni, B, e, s);               // dW = dZ^T h_{l-1}
+        hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, s, dZf, B, S_HID,
+                           G + layer_offset(l) + (int64_t)S_HID * ni);
+        if (l > 0) {
+            GemmEpi e2{};
+            e2.C = dH; e2.ldc = S_HID;
+            gemm<EPI_PLAIN>(dZb, S_HID, WbT[l], S_HID, B, S_HID, S_HID, e2, s);   // dh = dZ W
+        }
+    }
+}
+
+int Surrogate::compute_norm(const FeatSrc &f, const TgtSrc &t, hipStream_t s, char *err) {
+    const int nfeat = N + 3, nout = N + 1;
+    double *dm = nullptr;
+    SCHK(dalloc(&dm, (size_t)4 * nfeat + 2 * nout));
+    hipLaunchKernelGGL(k_feature_moments, dim3(nfeat), dim3(256), 0, s, f, nfeat, dm);
+    hipLaunchKernelGGL(k_target_moments, dim3(nout), dim3(256), 0, s, t, dm + 4 * nfeat);
+    std::vector<double> hm(4 * nfeat + 2 * nout);
+    SCHK(hipMemcpyAsync(hm.data(), dm, sizeof(double) * hm.size(), hipMemcpyDeviceToHost, s));
+    SCHK(hipStreamSynchronize(s));
+    (void)hipFree(dm);
+    std::vector<float> nb(6 * S_IN, 0.0f);
+    const double n = (double)f.n;
+    for (int c = 0; c < S_IN; ++c) { nb[64 + c] = 1.0f; nb[192 + c] = 1.0f; }
+    for (int c = 0; c < nfeat; ++c) {
+        const double mu = hm[4 * c] / n;
+        const double var = std::max(0.0, hm[4 * c + 1] / n - mu * mu);
+        const double sd = sqrt(var);
+        nb[c] = (float)mu;
+        nb[64 + c] = sd > 1e-30 ? (float)sd : 1.0f;
+        // the stored box must contain every training feature after rounding
+        float lo = (float)hm[4 * c + 2], hi = (float)hm[4 * c + 3];
+        if ((double)lo > hm[4 * c + 2]) lo = nextafterf(lo, -INFINITY);
+        if ((double)hi < hm[4 * c + 3]) hi = nextafterf(hi, INFINITY);
+        nb[256 + c] = lo;
+        nb[320 + c] = hi;
+    }
+    for (int c = 0; c < nout; ++c) {
+        const double mu = hm[4 * nfeat + 2 * c] / n;
+        const double var = std::max(0.0, hm[4 * nfeat + 2 * c + 1] / n - mu * mu);
+        const double sd = sqrt(var);
+        nb[128 + c] = (float)mu;
+        nb[192 + c] = sd > 1e-30 ? (float)sd : 1.0f;
+    }
+    SCHK(hipMemcpyAsync(P + weights_count(), nb.data(), sizeof(float) * nb.size(),
+                        hipMemcpyHostToDevice, s));
+    SCHK(hipStreamSynchronize(s));   // nb is released on return
+    return 0;
+}
+
+int Surrogate::train(const FeatSrc &f, const TgtSrc &t, int epochs, int B, double lr0, double lr1,
+                     uint64_t seed, float *loss_hist, int verbose, hipStream_t s, char *err) {
+    if (B % 64 != 0 || B < 64) { snprintf(err, 256, "batch must be a positive multiple of 64"); return -1; }
+    const int64_t n = f.n;
+    if (n < B) { snprintf(err, 256, "fewer samples than one batch"); return -1; }
+    int rc = reserve_ws(B, true, err);
+    if (rc) return rc;
+    rc = compute_norm(f, t, s, err);
+    if (rc) return rc;
+    // He-style initialisation (seeded), zero biases, small output layer
+    {
+        std::mt19937_64 rng(seed);
+        std::normal_distribution<float> nd(0.0f, 1.0f);
+        std::vector<float> h(weights_count(), 0.0f);
+        for (int l = 0; l < 5; ++l) {
+            const int no = layer_out(l), ni = layer_in(l);
+            const float sc = (l == 4 ? 0.1f : 1.0f) * sqrtf(2.0f / (float)ni);
+            float *W = h.data() + layer_offset(l);
+            for (int o = 0; o < no; ++o)
+                for (int i = 0; i < ni; ++i) {
+                    const bool live_in = l > 0 || i < N + 3;
+                    const bool live_out = l < 4 || o < N + 1;
+                    W[o * ni + i] = (live_in && live_out) ? sc * nd(rng) : 0.0f;
+                }
+        }
+        SCHK(hipMemcpyAsync(P, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice, s));
+        SCHK(hipMemsetAsync(mA, 0, sizeof(float) * weights_count(), s));
+        SCHK(hipMemsetAsync(vA, 0, sizeof(float) * weights_count(), s));
+        SCHK(hipStreamSynchronize(s));   // h is released at the end of this scope
+    }
+    rc = refresh(s, err);
+    if (rc) return rc;
+    const int64_t nb = n / B;
+    const int64_t total = nb * epochs;
+    int *d_perm = nullptr;
+    SCHK(dalloc(&d_perm, (size_t)n));
+    std::vector<int> perm(n);
+    std::mt19937_64 rng(seed ^ 0x9e3779b97f4a7c15ull);
+    int64_t step = 0;
+    const int64_t nw = weights_count();
+    for (int ep = 0; ep < epochs; ++ep) {
+        std::iota(perm.begin(), perm.end(), 0);
+        std::shuffle(perm.begin(), perm.end(), rng);
+        SCHK(hipMemcpyAsync(d_perm, perm.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+        SCHK(hipMemsetAsync(d_loss, 0, sizeof(double), s));
+        for (int64_t bi = 0; bi < nb; ++bi, ++step) {
+            hipLaunchKernelGGL(k_build_rows, dim3((B + 3) / 4), dim3(256), 0, s, f, t,
+                               d_perm + bi * B, (int64_t)0, B, P + weights_count(), X, XT, B, Tg);
+            forward(B, true, false, s);
+            backward(B, s);
+            const double frac = total > 1 ? (double)step / (double)(total - 1) : 1.0;
+            const float lr = (float)(lr1 + 0.5 * (lr0 - lr1) * (1.0 + cos(M_PI * frac)));
+            const float b1 = 0.9f, b2 = 0.999f;
+            const float c1 = 1.0f - powf(b1, (float)(step + 1)), c2 = 1.0f - powf(b2, (float)(step + 1));
+            hipLaunchKernelGGL(k_adam, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, P, G, mA,
+                               vA, nw, lr, b1, b2, 1e-8f, c1, c2);
+            int r2 = refresh(s, err);
+            if (r2) return r2;
+        }
+        double l = 0.0;
+        SCHK(hipMemcpyAsync(&l, d_loss, sizeof(double), hipMemcpyDeviceToHost, s));
+        SCHK(hipStreamSynchronize(s));
+        const double mean = l / ((double)nb * B * (N + 1));
+        if (loss_hist) loss_hist[ep] = (float)mean;
+        if (verbose) fprintf(stderr, "[libchem] surrogate epoch %d/%d: loss %.4e\n", ep + 1, epochs, mean);
+    }
+    SCHK(hipGetLastError());
+    (void)hipFree(d_perm);
+    trained = true;
+    return 0;
+}
+
+int Surrogate::loss_grad(const FeatSrc &f, const TgtSrc &t, float *grad_host, double *loss,
+                         hipStream_t s, char *err) {
+    const int B = (int)f.n;
+    if (B % 64 != 0 || B < 64 || B > 65536) { snprintf(err, 256, "n must be a multiple of 64, <= 65536"); return -1; }
+    int rc = reserve_ws(B, true, err);
+    if (rc) return rc;
+    SCHK(hipMemsetAsync(d_loss, 0, sizeof(double), s));
+    hipLaunchKernelGGL(k_build_rows, dim3((B + 3) / 4), dim3(256), 0, s, f, t, (const int *)nullptr,
+                       (int64_t)0, B, P + weights_count(), X, XT, B, Tg);
+    forward(B, true, false, s);
+    backward(B, s);
+    SCHK(hipMemcpyAsync(grad_host, G, sizeof(float) * weights_count(), hipMemcpyDeviceToHost, s));
+    double l = 0.0;
+    SCHK(hipMemcpyAsync(&l, d_loss, sizeof(double), hipMemcpyDeviceToHost, s));
+    SCHK(hipStreamSynchronize(s));
+    *loss = l / ((double)B * (N + 1));
+    return 0;
+}
+
+int Surrogate::forward_rows(const FeatSrc &f, float *out_dev, hipStream_t s, char *err) {
+    const int64_t n = f.n;
+    const int chunk = 65536;
+    int rc = reserve_ws((int)std::min<int64_t>(n, chunk), false, err);
+    if (rc) return rc;
+    TgtSrc t{};
+    for (int64_t base = 0; base < n; base += chunk) {
+        const int m = (int)std::min<int64_t>(chunk, n - base);
+        hipLaunchKernelGGL(k_build_rows, dim3((m + 3) / 4), dim3(256), 0, s, f, t, (const int *)nullptr,
+                           base, m, P + weights_count(), X, (uint16_t *)nullptr, 0, (float *)nullptr);
+        forward(m, false, false, s);
+        SCHK(hipMemcpyAsync(out_dev + base * S_OUT, out, sizeof(float) * m * S_OUT,
+                            hipMemcpyDeviceToDevice, s));
+    }
+    SCHK(hipGetLastError());
+    return 0;
+}
+
+int Surrogate::apply(const FeatSrc &f, double *T, double *Y, uint8_t *flags, const PostIn &pin,
+                     unsigned long long *stats, hipStream_t s, char *err) {
+    const int64_t n = f.n;
+    const int chunk = 262144;
+    int rc = reserve_ws((int)std::min<int64_t>(n, chunk), false, err);
+    if (rc) return rc;
+    PostParams q{};
+    q.N = N; q.nel = nel; q.E = E; q.Ginv = Ginv; q.nasa_t = pin.nasa_t; q.invW = pin.invW;
+    q.norm = P + weights_count(); q.tau_T = pin.tau_T; q.y_min = pin.y_min; q.margin = pin.margin;
+    TgtSrc t{};
+    for (int64_t base = 0; base < n; base += chunk) {
+        const int m = (int)std::min<int64_t>(chunk, n - base);
+        hipLaunchKernelGGL(k_build_rows, dim3((m + 3) / 4), dim3(256), 0, s, f, t, (const int *)nullptr,
+                           base, m, P + weights_count(), X, (uint16_t *)nullptr, 0, (float *)nullptr);
+        forward(m, false, true, s);
+        hipLaunchKernelGGL(k_surrogate_post, dim3((m + 255) / 256), dim3(256), 0, s, f, base, m, out, q, T,
+                           Y, flags, stats);
+    }
+    SCHK(hipGetLastError());
+    return 0;
+}
+
+}  // namespace chem

@@ -391,3 +391,71 @@ def stratified_indices(f: Field, per_class: int, seed: int = 7):
         take = min(per_class, ids.size)
         out.append(np.sort(rng.choice(ids, size=take, replace=False)))
     return np.concatenate(out)
+
+
+# ------------------------------------------------------- surrogate inputs ---
+SUR_DIMS = (64, 256, 256, 256, 256, 64)   # padded layer widths of the surrogate network
+
+
+def surrogate_params(n_species: int, seed: int = 0, weight_scale: float = 1.0,
+                     dY_scale: float = 1e-4, dT_scale: float = 10.0, zero_output_weights=False,
+                     box=None) -> np.ndarray:
+    """Seeded float32 parameter blob in the surrogate's layout, for tests.
+
+    Layer l: W [out x in] ~ N(0, weight_scale^2 / in) on the live rows and
+    columns (n_species + 3 inputs, n_species + 1 outputs), zero on the padding;
+    b ~ N(0, 0.1^2) on live outputs.  zero_output_weights makes the output
+    layer's W zero, so the network output equals its bias exactly.
+    Normalisation: features centred on (ln 1000 K, ln 1 atm, 0.02, ln 1e-6 s)
+    with spreads (0.5, 1, 0.1, 1); outputs scaled by dY_scale per species and
+    dT_scale for T.  box = (xmin, xmax) arrays of the N + 3 live features, or
+    None for an unbounded box."""
+    N = int(n_species)
+    rng = _rng(seed)
+    nfeat, nout = N + 3, N + 1
+    blob = []
+    for l in range(5):
+        ni, no = SUR_DIMS[l], SUR_DIMS[l + 1]
+        live_i = nfeat if l == 0 else ni
+        live_o = nout if l == 4 else no
+        W = np.zeros((no, ni))
+        b = np.zeros(no)
+        if not (l == 4 and zero_output_weights):
+            W[:live_o, :live_i] = rng.standard_normal((live_o, live_i)) * weight_scale / np.sqrt(ni)
+        b[:live_o] = rng.standard_normal(live_o) * 0.1
+        blob += [W.ravel(), b]
+    mu_x = np.zeros(64)
+    sd_x = np.ones(64)
+    mu_x[0], sd_x[0] = np.log(1000.0), 0.5
+    mu_x[1], sd_x[1] = np.log(P_ATM), 1.0
+    mu_x[2:2 + N], sd_x[2:2 + N] = 0.02, 0.1
+    mu_x[2 + N], sd_x[2 + N] = np.log(1e-6), 1.0
+    mu_o = np.zeros(64)
+    sd_o = np.ones(64)
+    sd_o[:N] = dY_scale
+    sd_o[N] = dT_scale
+    xmin = np.full(64, -1e30)
+    xmax = np.full(64, 1e30)
+    if box is not None:
+        xmin[:nfeat] = box[0]
+        xmax[:nfeat] = box[1]
+    blob += [mu_x, sd_x, mu_o, sd_o, xmin, xmax]
+    return np.concatenate(blob).astype(np.float32)
+
+
+def surrogate_pairs_field(n_cells: int, seed: int = 900) -> Field:
+    """Initial states for solver-generated training pairs: the mixed
+    cold / mixing-layer / igniting distribution with its own seed."""
+    return field_mapped(n_cells, seed, n_steps=1)
+
+
+def surrogate_dt(n: int, seed: int, dt0=1e-6, lo=2.5e-7, hi=4e-6, levels=16):
+    """Per-sample steps: half exactly dt0, half drawn uniformly from `levels`
+    log-spaced values spanning [lo, hi] (a discrete log-uniform law, so that
+    the solver runs one call per distinct step)."""
+    rng = _rng(seed)
+    dt = np.full(n, dt0)
+    k = rng.permutation(n)[: n // 2]
+    grid = np.exp(np.linspace(np.log(lo), np.log(hi), levels))
+    dt[k] = grid[rng.integers(0, levels, size=k.size)]
+    return dt

@@ -38,3 +38,17 @@ def test_no_compute_without_context():
     assert L.chem_set_options(None, ctypes.byref(o)) == -1
     assert L.chem_integrate(None, 0, None, None, None, 1e-6, None, None, None, None, None,
                             None, None) == -1
+
+
+def test_surrogate_defaults_without_gpu():
+    L = chem.load_library()
+    assert L.chem_surrogate_param_count() == 230848
+    tp = chem.TrainParams()
+    L.chem_default_train_params(ctypes.byref(tp))
+    assert tp.batch % 64 == 0 and tp.epochs >= 1 and tp.lr_max > tp.lr_min >= 0
+    g = chem.GateParams()
+    L.chem_default_gate_params(ctypes.byref(g))
+    assert g.tau_T == 0.5 and g.y_min == -1e-10 and g.margin == 0.0
+    assert L.chem_surrogate_train(None, 0, None, None, None, None, None, None,
+                                  ctypes.byref(tp), None) == -1
+    assert L.chem_surrogate_load(None, b"/nonexistent") == -1
