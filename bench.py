@@ -2,14 +2,17 @@
 """Throughput of the per-cell chemistry hot path on one MI355X.
 
 A step is one pass of the whole path over the field: reference mapping
-(Sec. 2.3 criterion), heavy-first work-queue construction from the previous
-step's per-cell cost, persistent-kernel Rodas4 integration of every unmapped
-cell, and the enthalpy-consistent update of mapped cells.  Consecutive steps
-advance the same field, as consecutive flow time steps would.
+(Sec. 2.3 criterion), the learned surrogate with its conservation step and
+gate on the cells mapping leaves (headline mode), heavy-first work-queue
+construction from the previous step's per-cell cost, persistent-kernel Rodas4
+integration of every remaining cell, and the enthalpy-consistent update of
+mapped cells.  Consecutive steps advance the same field, as consecutive flow
+time steps would.
 
 Prints one JSON line: cells*dt/s of that path, the plain static-launch
-integration of the same field for comparison, the integration kernel's
-roofline position, and the CPU oracle timed on a bounded sample.
+integration and the balanced path without the surrogate on the same field for
+comparison, the surrogate's error against the CPU oracle, the integration
+kernel's roofline position, and the CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -42,41 +45,182 @@ def make_state(field, torch):
                 ref=torch.zeros(1, dtype=torch.int64, device="cuda"))
 
 
-def run_mode(chem, mech, field, mode, steps, warmup, torch, synth):
-    """Returns (ms_per_step, per-step stats of the timed steps)."""
+def run_mode(chem, mech, field, mode, steps, warmup, torch, synth, record_idx=None, gate=None):
+    """Returns (ms_per_step, per-step stats of the timed steps, record, state).
+    record: host copies of T, Y and flags of record_idx after the first step
+    (taken in the untimed warm-up)."""
     from paper_2011_07978_amd.chem import CHEM_SCHED_PLAIN, CHEM_SCHED_QUEUE
     S = make_state(field, torch)
     Yf, Yo = synth.stream_fuel(mech), synth.stream_oxidiser(mech)
-    if mode == "plain":
-        chem.set_options(schedule=CHEM_SCHED_PLAIN)
-    else:
-        chem.set_options(schedule=CHEM_SCHED_QUEUE)
+    chem.set_options(schedule=CHEM_SCHED_PLAIN if mode == "plain" else CHEM_SCHED_QUEUE)
 
-    def one_step():
+    def one_step(S):
         if mode == "plain":
             return chem.integrate(S["T"], S["p"], S["Y"], field.dt, h=S["h"], cost=S["cost"],
                                   status=S["status"], stats=True)
         chem.map_reference(S["T"], S["p"], S["Y"], Yf, Yo, 1e-4, 1.0, False,
                            flags=S["flags"], ref_index=S["ref"])
+        if mode == "surrogate":
+            return chem.integrate_surrogate(S["T"], S["p"], S["Y"], field.dt, S["flags"], S["ref"],
+                                            gate=gate, h=S["h"], cost=S["cost"],
+                                            status=S["status"], stats=True)
         return chem.integrate(S["T"], S["p"], S["Y"], field.dt, flags=S["flags"],
                               ref_index=S["ref"], h=S["h"], cost=S["cost"], status=S["status"],
                               stats=True)
 
+    record = None
     for w in range(warmup):
-        st = one_step()
+        st = one_step(S)
         log(f"{mode} warmup {w + 1}/{warmup}: {st['ms_total']:.1f} ms, "
-            f"steps {st['steps_accepted']}+{st['steps_rejected']}")
+            f"steps {st['steps_accepted']}+{st['steps_rejected']}, surrogate {st['cells_surrogate']}")
+        if w == 0 and record_idx is not None:
+            ix = torch.as_tensor(record_idx, device="cuda")
+            record = dict(T=S["T"][ix].cpu().numpy(), Y=S["Y"][:, ix].cpu().numpy(),
+                          flags=S["flags"][ix].cpu().numpy())
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = []
     for k in range(steps):
-        st = one_step()
+        st = one_step(S)
         stats.append(st)
         log(f"{mode} step {k + 1}/{steps}: {st['ms_total']:.1f} ms (integrate kernel "
-            f"{st['ms_integrate']:.1f} ms), mapped {st['cells_mapped']}, failed {st['cells_failed']}")
+            f"{st['ms_integrate']:.1f} ms, surrogate {st['ms_surrogate']:.2f} ms), mapped "
+            f"{st['cells_mapped']}, surrogate {st['cells_surrogate']}, failed {st['cells_failed']}")
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
-    return ms, stats
+    S["one_step"] = one_step
+    return ms, stats, record, S
+
+
+def graph_replay(chem, mech, field, steps, warmup, torch, synth):
+    """The balanced path's steps recorded once into a HIP graph (chem_graph_*)
+    and replayed: the same kernels without per-step host launches.  Returns
+    ms per step of one replay of `steps` recorded steps."""
+    from paper_2011_07978_amd.chem import CHEM_SCHED_QUEUE, Chem
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        g = Chem(0, stream=stream)
+        g.set_mechanism(mech)
+        g.set_options(**{k: getattr(chem.options(), k) for k in ("queue_chunk", "slots_per_cu")},
+                      schedule=CHEM_SCHED_QUEUE)
+        g.reserve(field.n_cells)
+        S = make_state(field, torch)
+        Yf, Yo = synth.stream_fuel(mech), synth.stream_oxidiser(mech)
+
+        def step():
+            g.map_reference(S["T"], S["p"], S["Y"], Yf, Yo, 1e-4, 1.0, False, flags=S["flags"],
+                            ref_index=S["ref"])
+            g.integrate(S["T"], S["p"], S["Y"], field.dt, flags=S["flags"], ref_index=S["ref"],
+                        h=S["h"], cost=S["cost"], status=S["status"])
+        for _ in range(max(1, warmup)):
+            step()
+        stream.synchronize()
+        g.graph_begin()
+        for _ in range(steps):
+            step()
+        graph = g.graph_end()
+        stream.synchronize()
+        t0 = time.perf_counter()
+        graph.launch()
+        stream.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        graph.close()
+    log(f"graph replay of {steps} steps: {ms:.1f} ms per step")
+    return ms
+
+
+def train_surrogate(chem, mech, args, torch, accounting):
+    """Solver-generated pairs and training (untimed, reported separately)."""
+    from paper_2011_07978_amd import surrogate
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pairs = surrogate.generate_pairs(chem, n_cells=args.sur_cells, n_steps=args.sur_steps, seed=900,
+                                     log=lambda m: log(m))
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t0
+    tr, va = surrogate.split(pairs)
+    t0 = time.perf_counter()
+    hist = surrogate.train(chem, tr, epochs=args.sur_epochs, batch=4096, seed=1)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"surrogate: {pairs.n} pairs in {t_pairs:.1f} s, {args.sur_epochs} epochs in {t_train:.1f} s, "
+        f"loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+    val = surrogate.validate(chem, va, gate=dict(tau_T=args.tau_T))
+    fl = accounting.surrogate_train_flops_per_sample(mech.n_species) * tr.n * args.sur_epochs
+    return dict(pairs=pairs.n, train_pairs=tr.n, validation_pairs=va.n, epochs=args.sur_epochs,
+                seconds_pairs=t_pairs, seconds_train=t_train,
+                train_samples_per_s=tr.n * args.sur_epochs / t_train,
+                train_bf16_tflops=fl / t_train / 1e12, loss_history=[float(x) for x in hist],
+                validation={k: v for k, v in val.items() if k != "stats"})
+
+
+def first_step_error(mech, field, synth, rec, idx, threads):
+    """The oracle's first step (mapping on the full field, exact integration of
+    the unmapped sample cells and of the reference cell, mapped update) against
+    the GPU path's first step on a stratified sample."""
+    from oracle import Oracle
+    o = Oracle(mech)
+    Yf, Yo = synth.stream_fuel(mech), synth.stream_oxidiser(mech)
+    flags_full, ref = o.map_reference(field.T, field.Y, Yf, Yo, 1e-4)
+    cells = list(idx)
+    ref_pos = -1
+    if ref >= 0:
+        if ref in cells:
+            ref_pos = cells.index(ref)
+        else:
+            cells.append(ref)
+            ref_pos = len(cells) - 1
+    sub = synth.subsample(field, np.asarray(cells))
+    t0 = time.perf_counter()
+    To, Yo_ = o.step_mapped(sub.T, sub.p, sub.Y, field.dt, flags_full[cells], ref_pos,
+                            threads=threads, schedule=1)[:2]
+    secs = time.perf_counter() - t0
+    m = len(idx)
+    dT = np.abs(rec["T"] - To[:m])
+    dY = np.abs(rec["Y"] - Yo_[:, :m]).max(axis=0)
+    acc = rec["flags"] == 3
+    cls = field.cls[idx]
+    out = dict(sample=f"{m} cells, stratified by class ({', '.join(field.class_names)}), seed 7; "
+                      f"oracle {secs:.1f} s on {threads} threads",
+               mean_abs_dT=float(dT.mean()), max_abs_dT=float(dT.max()), max_abs_dY=float(dY.max()),
+               by_class={})
+    weights = np.bincount(field.cls, minlength=len(field.class_names)) / field.n_cells
+    whole = 0.0
+    for c, name in enumerate(field.class_names):
+        sel = cls == c
+        if not sel.any():
+            continue
+        a = sel & acc
+        out["by_class"][name] = dict(cells=int(sel.sum()), surrogate=int(a.sum()),
+                                     mean_abs_dT=float(dT[sel].mean()),
+                                     max_abs_dT=float(dT[sel].max()),
+                                     max_abs_dY=float(dY[sel].max()),
+                                     mean_abs_dT_surrogate=float(dT[a].mean()) if a.any() else None)
+        whole += weights[c] * float(dT[sel].mean())
+    out["field_mean_abs_dT_by_class_weights"] = whole
+    a = acc
+    out["surrogate_cells_mean_abs_dT"] = float(dT[a].mean()) if a.any() else None
+    out["surrogate_cells_max_abs_dT"] = float(dT[a].max()) if a.any() else None
+    return out
+
+
+def steady_state_error(chem, S, torch, surrogate_step, balanced_step):
+    """From the current steady state: one step with the surrogate against the
+    same step by the FP64 path (mapping + Rosenbrock), on surrogate cells."""
+    A = {k: (v.clone() if torch.is_tensor(v) else v) for k, v in S.items()}
+    B = {k: (v.clone() if torch.is_tensor(v) else v) for k, v in S.items()}
+    surrogate_step(A)
+    balanced_step(B)
+    torch.cuda.synchronize()
+    acc = A["flags"] == 3
+    n_acc = int(acc.sum())
+    if n_acc == 0:
+        return dict(surrogate_cells=0)
+    dT = (A["T"] - B["T"]).abs()[acc]
+    dY = (A["Y"] - B["Y"]).abs()[:, acc].amax(dim=0)
+    return dict(surrogate_cells=n_acc, mean_abs_dT=float(dT.mean()), max_abs_dT=float(dT.max()),
+                p99_abs_dT=float(torch.quantile(dT[:1 << 20].float(), 0.99)),
+                max_abs_dY=float(dY.max()))
 
 
 def cpu_baseline(mech, field, synth, warmup, steps, budget_s=20.0, threads=None):
@@ -133,8 +277,18 @@ def main():
     ap.add_argument("--cells", type=int, default=0, help="override the field size")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-error", action="store_true", help="skip the oracle error sample")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="CPU budget of the oracle warm-up (sizes the sample)")
+    ap.add_argument("--error-per-class", type=int, default=512)
+    ap.add_argument("--sur-cells", type=int, default=262144, help="cells of the pair field")
+    ap.add_argument("--sur-steps", type=int, default=8, help="flow steps of the pair field")
+    ap.add_argument("--sur-epochs", type=int, default=8)
+    ap.add_argument("--tau-T", type=float, default=0.5)
+    ap.add_argument("--graph", action="store_true",
+                    help="also time the balanced steps recorded into one HIP graph")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick queue chunk and slots per CU on the first step's state first")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -151,53 +305,114 @@ def main():
     wl = synth.WORKLOADS[args.workload]
     mech = synth.mechanism(wl["mech"])
     field = wl["field"](args.cells) if args.cells else wl["field"]()
+    use_sur = args.workload == "surrogate"
     log(f"workload {args.workload}: {field.n_cells} cells, {mech.n_species} species, "
         f"{mech.n_reactions} reactions, dt {field.dt}")
     chem = Chem(0)
     chem.set_mechanism(mech)
-    chem.reserve(field.n_cells)
+    threads = min(16, os.cpu_count() or 1)
 
-    ms_bal, st_bal = run_mode(chem, mech, field, "balanced", args.steps, args.warmup, torch, synth)
-    value = field.n_cells / (ms_bal / 1e3)
+    sur = None
+    gate = dict(tau_T=args.tau_T, y_min=-1e-10, margin=0.0)
+    if use_sur:
+        sur = train_surrogate(chem, mech, args, torch, accounting)
+    chem.reserve(field.n_cells)
+    tune = None
+    if args.autotune:
+        S0 = make_state(field, torch)
+        tune = chem.autotune(S0["T"], S0["p"], S0["Y"], field.dt)
+        o = chem.options()
+        log(f"autotune: {tune} -> schedule {o.schedule} chunk {o.queue_chunk} slots {o.slots_per_cu}")
+        del S0
+
+    rec_idx = None
+    if use_sur and not args.no_error and args.warmup >= 1:
+        rec_idx = synth.stratified_indices(field, args.error_per_class, seed=7)
+
+    head_mode = "surrogate" if use_sur else "balanced"
+    ms_h, st_h, rec, S_h = run_mode(chem, mech, field, head_mode, args.steps, args.warmup, torch,
+                                    synth, record_idx=rec_idx, gate=gate)
+    value = field.n_cells / (ms_h / 1e3)
+    balanced = None
+    if use_sur:
+        ms_b, st_b, _, S_b = run_mode(chem, mech, field, "balanced", args.steps, args.warmup, torch,
+                                      synth)
+        balanced = dict(value=field.n_cells / (ms_b / 1e3), ms_per_step=ms_b,
+                        integrate_ms=float(np.mean([s["ms_integrate"] for s in st_b])))
+        sur["steady_state_vs_fp64_path"] = steady_state_error(chem, S_h, torch, S_h["one_step"],
+                                                              S_b["one_step"])
+        del S_b
     plain = None
     if not args.no_plain:
-        ms_pl, st_pl = run_mode(chem, mech, field, "plain", args.steps, args.warmup, torch, synth)
+        ms_pl, st_pl, _, S_p = run_mode(chem, mech, field, "plain", args.steps, args.warmup, torch,
+                                        synth)
         plain = dict(value=field.n_cells / (ms_pl / 1e3), ms_per_step=ms_pl,
                      integrate_ms=float(np.mean([s["ms_integrate"] for s in st_pl])))
+        del S_p
+
+    graph = None
+    if args.graph:
+        ms_g = graph_replay(chem, mech, field, args.steps, args.warmup, torch, synth)
+        graph = dict(ms_per_step=ms_g, value=field.n_cells / (ms_g / 1e3),
+                     note="balanced path (no surrogate), steps recorded into one HIP graph")
 
     # roofline of the dominant kernel (the integration kernel), per launch
     sc = accounting.step_cost(mech)
-    fl = [sc.flops(s["steps_accepted"], s["steps_rejected"]) for s in st_bal]
-    kms = [s["ms_integrate"] for s in st_bal]
+    fl = [sc.flops(s["steps_accepted"], s["steps_rejected"]) for s in st_h]
+    kms = [s["ms_integrate"] for s in st_h]
     achieved = float(np.mean([f / (m * 1e-3) / 1e12 for f, m in zip(fl, kms)]))
+    kname = "k_big_queue" if mech.n_species + 1 > 64 else "k_integrate_queue"
     roof = dict(bound="alu", achieved=achieved, peak=accounting.FP64_VECTOR_PEAK_TFLOPS,
                 unit="TFLOP/s", frac=achieved / accounting.FP64_VECTOR_PEAK_TFLOPS, traffic=None,
-                kernel="k_integrate_queue", kernel_ms=float(np.mean(kms)),
+                kernel=kname, kernel_ms=float(np.mean(kms)),
                 flops_per_launch=float(np.mean(fl)),
                 steps_per_launch=float(np.mean([s["steps_accepted"] + s["steps_rejected"]
-                                                for s in st_bal])),
+                                                for s in st_h])),
                 transcendentals_per_launch=float(np.mean(
-                    [sc.transcendentals(s["steps_accepted"], s["steps_rejected"]) for s in st_bal])))
+                    [sc.transcendentals(s["steps_accepted"], s["steps_rejected"]) for s in st_h])))
+
+    if use_sur:
+        n_try = np.mean([s["cells_surrogate"] + s["cells_rejected"] for s in st_h])
+        ms_s = float(np.mean([s["ms_surrogate"] for s in st_h]))
+        f_inf = accounting.surrogate_flops_per_cell(mech.n_species) * n_try
+        sur.update(gate=gate, cells_offered_per_step=float(n_try),
+                   cells_accepted_per_step=float(np.mean([s["cells_surrogate"] for s in st_h])),
+                   ms_surrogate_per_step=ms_s,
+                   inference_bf16_tflops=f_inf / (ms_s * 1e-3) / 1e12 if ms_s > 0 else None,
+                   inference_bf16_frac=(f_inf / (ms_s * 1e-3) / 1e12 / accounting.BF16_MFMA_PEAK_TFLOPS)
+                   if ms_s > 0 else None)
+        if rec is not None:
+            log("oracle first-step error on a stratified sample ...")
+            sur["first_step_error_vs_oracle"] = first_step_error(mech, field, synth, rec, rec_idx,
+                                                                 threads)
 
     cpu = None
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample ...")
-        cpu = cpu_baseline(mech, field, synth, args.warmup, args.steps, budget_s=args.cpu_seconds)
+        cpu = cpu_baseline(mech, field, synth, args.warmup, args.steps, budget_s=args.cpu_seconds,
+                           threads=threads)
 
+    desc = (f"{args.workload}: {field.n_cells} cells, {mech.n_species} species / "
+            f"{mech.n_reactions} reactions, dt {field.dt} s, rtol 1e-8, atol 1e-12, map (Z_tol 1e-4)"
+            + (" + BF16 MLP surrogate with conservation and gate (tau_T %g K)" % args.tau_T
+               if use_sur else "")
+            + " + heavy-first queue + Rodas4 + mapped update")
     out = {
         "metric": METRIC, "value": value, "unit": "cells·dt/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_bal,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_h,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {field.n_cells} cells, {mech.n_species} species / "
-                               f"{mech.n_reactions} reactions, dt {field.dt} s, rtol 1e-8, atol 1e-12, "
-                               "map (Z_tol 1e-4) + heavy-first queue + Rodas4 + mapped update",
-                   "cells": field.n_cells, "species": mech.n_species,
+        "config": {"workload": desc, "cells": field.n_cells, "species": mech.n_species,
                    "reactions": mech.n_reactions, "dt": field.dt, "parallelism": "single GPU"},
         "plain": plain,
+        "balanced_without_surrogate": balanced,
         "speedup_vs_plain": (value / plain["value"]) if plain else None,
-        "mapped_cells_per_step": float(np.mean([s["cells_mapped"] for s in st_bal])),
-        "failed_cells": int(sum(s["cells_failed"] for s in st_bal)),
+        "speedup_vs_balanced": (value / balanced["value"]) if balanced else None,
+        "mapped_cells_per_step": float(np.mean([s["cells_mapped"] for s in st_h])),
+        "failed_cells": int(sum(s["cells_failed"] for s in st_h)),
+        "surrogate": sur,
+        "graph_replay": graph,
+        "autotune": tune,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -143,19 +143,24 @@ typedef struct {
  *   features x = (ln T, ln p, Y_1..Y_N, ln dt), normalised with the training
  *     set's mean and standard deviation, zero-padded to 64;
  *   four hidden layers of 256 with GELU (erf form); output 64, of which the
- *     first N+1 are the normalised increments (dY_1..dY_N, dT).
+ *     first N+1 are the normalised increments in an inverse hyperbolic-sine
+ *     scale: t = o sd_o + mu_o, dY_k = 1e-12 sinh(t_k), dT = 1e-6 K sinh(t_N)
+ *     (error relative to each increment's size across its many decades).
  * Weights and activations are bfloat16 (round to nearest even), products
  * accumulate in FP32 on the matrix cores, biases and GELU in FP32.
  * Parameter blob (float32, chem_surrogate_param_count() entries): layer by
  * layer W_l [out x in] row-major then b_l [out] (dims 64-256-256-256-256-64),
  * then six blocks of 64: mu_x, sd_x (feature normalisation), mu_o, sd_o
  * (output de-normalisation), xmin, xmax (training range of the raw features).
- * Each prediction dY is projected onto element conservation,
- *   dY <- dY - E^T (E E^T)^-1 E dY,  E_ek = a_ek / W_k,
- * and T' solves h(T', Y + dY) = h(T, Y).  The gate (chem_gate_params) sends a
- * cell back to the Rosenbrock solver unless every raw feature lies in
- * [xmin - margin*(xmax - xmin), xmax + margin*(xmax - xmin)], every
- * Y_k + dY_k >= y_min and |T + dT - T'| <= tau_T.
+ * The predicted state is clipped at zero, Y1 = max(Y + dY, 0), and element
+ * conservation restored by the correction smallest in the metric weighted by
+ * 1/Y1: Y' = Y1 - Y1 (E^T lam), (E diag(Y1) E^T) lam = E (Y1 - Y),
+ * E_ek = a_ek / W_k (species at zero stay there; corrections are proportional
+ * to each species' mass fraction).  T' solves h(T', Y') = h(T, Y).  The gate
+ * (chem_gate_params) sends a cell back to the Rosenbrock solver unless every
+ * raw feature lies in [xmin - margin*(xmax - xmin), xmax + margin*(xmax -
+ * xmin)], E diag(Y1) E^T is invertible, every Y'_k >= y_min and
+ * |T + dT - T'| <= tau_T.
  * Available for N <= 61 species and E <= 8 elements with E E^T invertible
  * (otherwise the surrogate entry points return CHEM_E_UNIMPL). */
 typedef struct {
@@ -188,7 +193,12 @@ const char *chem_last_error(const chem_ctx *ctx);
  * [200, 10000] K, A <= 0, indices out of range, efficiencies on
  * non-third-body reactions (CHEM_E_BAD_MECHANISM).  Synchronous. */
 int chem_set_mechanism(chem_ctx *ctx, const chem_mech_desc *m);
-/* largest species count the integrator handles: 63 species (64 unknowns) */
+/* Largest species count the integrator handles: 137 (138 unknowns).  Up to
+ * 63 species a wavefront integrates a cell with its iteration matrix in
+ * registers; above that a workgroup of four wavefronts integrates a cell with
+ * the n x n matrix in LDS (n^2 doubles plus ~9 n, which must fit in one CU's
+ * LDS: chem_set_mechanism's integrator calls return CHEM_E_UNIMPL when it does
+ * not on the device at hand) and a blocked LU on the FP64 matrix cores. */
 int chem_max_species(void);
 
 int chem_set_options(chem_ctx *ctx, const chem_options *o);

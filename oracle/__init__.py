@@ -280,10 +280,12 @@ def mlp_loss_grad(params, X, target, nfeat, nout, bf16_emulation=False):
     return loss, g
 
 
-def project(o, dY):
-    d = _f64(dY).copy()
-    lib().orc_project(o.h, _p(d))
-    return d
+def conserve(o, Y0, Y1):
+    """Clipped prediction Y1 corrected to conserve the elements of Y0; None if
+    the weighted element matrix is singular."""
+    y = _f64(Y1).copy()
+    rc = lib().orc_conserve(o.h, _p(_f64(Y0)), _p(y))
+    return None if rc else y
 
 
 def surrogate_cell(o, params, p, T, Y, dt, tau_T=0.5, y_min=-1e-10, margin=0.0):

@@ -7,18 +7,27 @@
  *             padded with zeros to IN_PAD,
  *   layers    h_{l} = GELU(W_l h_{l-1} + b_l), four hidden layers of width H,
  *             GELU(z) = z/2 (1 + erf(z / sqrt 2)),
- *   output    o = W_5 h_4 + b_5, normalised (dY_1..dY_N, dT).
+ *   output    o = W_5 h_4 + b_5: the normalised increments in an inverse
+ *             hyperbolic-sine scale, t = o * sd_o + mu_o,
+ *             dY_k = S_Y sinh(t_k), dT = S_T sinh(t_N), S_Y = 1e-12, S_T = 1e-6 K,
+ *             so that the network's error is relative to each increment's own
+ *             size over the many decades the increments span (linear below
+ *             S_Y and S_T, logarithmic above).
  * With bf16 emulation on, inputs, weights and hidden activations are rounded
  * to bfloat16 (round to nearest even) before each product, as the GPU path
  * stores them; every sum is accumulated in FP64.
  * Parameter blob (floats), layer by layer: W_l [out_pad x in_pad] then
  * b_l [out_pad]; then mu_x, sd_x, mu_o, sd_o, xmin, xmax (IN_PAD each).
  *
- * Projection onto element conservation: with E_ek = a_ek / W_k,
- *   dY <- dY - E^T (E E^T)^-1 E dY,
- * the minimum-norm correction that makes sum_k a_ek dY_k / W_k = 0 for every
- * element (and so sum_k dY_k = 0).  The temperature then follows from
- * h(T', Y') = h(T, Y) as for mapped cells. */
+ * Conservation: the predicted state Y + dY is first clipped at zero, then
+ * element conservation is restored by the correction that is smallest in the
+ * metric weighted by the inverse of the clipped mass fractions,
+ *   Y1 = max(Y + dY, 0),  delta_k = Y1_k (E^T lam)_k,
+ *   (E W E^T) lam = E (Y1 - Y),  W = diag(Y1),  E_ek = a_ek / W_k,
+ * so sum_k a_ek (Y1_k - delta_k - Y_k) / W_k = 0 for every element (and so
+ * sum_k of the increments is 0), species clipped to zero stay at zero, and
+ * each correction is proportional to the species' own mass fraction.  The
+ * temperature then follows from h(T', Y') = h(T, Y) as for mapped cells. */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -28,6 +37,8 @@
 #define IN_PAD 64
 #define HID 256
 #define OUT_PAD 64
+#define S_Y 1e-12
+#define S_T 1e-6
 
 static const int dims[6] = {IN_PAD, HID, HID, HID, HID, OUT_PAD};
 
@@ -189,36 +200,35 @@ double orc_mlp_loss_grad(const float *P, int64_t n, int nfeat, int nout, const d
     return loss * scale;
 }
 
-/* element-conservation projection of dY (length N) */
-void orc_project(const omech *m, double *dY)
+/* Element conservation of a clipped prediction (see the header): Y1 (length
+ * N, non-negative) is corrected in place towards conserving the elements of
+ * Y0.  Returns 0, or 1 if E W E^T is singular (Y1 unchanged). */
+int orc_conserve(const omech *m, const double *Y0, double *Y1)
 {
     const int E = m->E, N = m->N;
     double G[64], r[8], lam[8];
-    if (E > 8) return;
-    for (int a = 0; a < E; ++a)
-        for (int b = 0; b < E; ++b) {
-            double s = 0.0;
-            for (int k = 0; k < N; ++k)
-                s += (double)m->comp[k * E + a] / m->W[k] * (double)m->comp[k * E + b] / m->W[k];
-            G[a * E + b] = s;
-        }
+    int piv[8];
+    if (E > 8) return 1;
     for (int a = 0; a < E; ++a) {
         double s = 0.0;
-        for (int k = 0; k < N; ++k) s += (double)m->comp[k * E + a] / m->W[k] * dY[k];
+        for (int k = 0; k < N; ++k) s += (double)m->comp[k * E + a] / m->W[k] * (Y1[k] - Y0[k]);
         r[a] = s;
+        for (int b = 0; b < E; ++b) {
+            double g = 0.0;
+            for (int k = 0; k < N; ++k)
+                g += (double)m->comp[k * E + a] / m->W[k] * Y1[k] * ((double)m->comp[k * E + b] / m->W[k]);
+            G[a * E + b] = g;
+        }
     }
-    /* solve G lam = r (symmetric positive definite, small): Gaussian elimination */
-    int piv[8];
-    double A[64];
-    memcpy(A, G, sizeof(double) * E * E);
-    if (orc_lu(E, A, piv) != 0) return;
+    if (orc_lu(E, G, piv) != 0) return 1;
     memcpy(lam, r, sizeof(double) * E);
-    orc_lu_solve(E, A, piv, lam);
+    orc_lu_solve(E, G, piv, lam);
     for (int k = 0; k < N; ++k) {
         double s = 0.0;
         for (int a = 0; a < E; ++a) s += (double)m->comp[k * E + a] / m->W[k] * lam[a];
-        dY[k] -= s;
+        Y1[k] -= Y1[k] * s;
     }
+    return 0;
 }
 
 /* One surrogate step for one cell (raw state in/out); returns 1 if the gate
@@ -237,14 +247,15 @@ int orc_surrogate_cell(const omech *m, const float *P, double p, double *T, doub
         if (x[i] < xmin[i] - margin * span || x[i] > xmax[i] + margin * span) return 0;
     }
     orc_mlp_forward(P, 1, N + 3, x, 1, out, NULL, NULL);
-    double dY[N], Yn[N];
-    for (int k = 0; k < N; ++k) dY[k] = out[k] * sd_o[k] + mu_o[k];
-    const double dT = out[N] * sd_o[N] + mu_o[N];
-    orc_project(m, dY);
+    double Yn[N];
     for (int k = 0; k < N; ++k) {
-        Yn[k] = Y[k] + dY[k];
-        if (!(Yn[k] >= y_min)) return 0;
+        const double yk = Y[k] + S_Y * sinh(out[k] * sd_o[k] + mu_o[k]);
+        Yn[k] = yk > 0.0 ? yk : 0.0;
     }
+    const double dT = S_T * sinh(out[N] * sd_o[N] + mu_o[N]);
+    if (orc_conserve(m, Y, Yn) != 0) return 0;
+    for (int k = 0; k < N; ++k)
+        if (!(Yn[k] >= y_min)) return 0;
     const double h = orc_enthalpy_mass(m, *T, Y);
     const double Th = orc_temperature_from_enthalpy(m, h, Yn, *T + dT, NULL);
     if (!(fabs(*T + dT - Th) <= tau_T)) return 0;

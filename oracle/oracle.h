@@ -142,7 +142,7 @@ void orc_mlp_forward(const float *P, int64_t n, int nfeat, const double *X, int 
                      double *out, double *acts, double *pre);
 double orc_mlp_loss_grad(const float *P, int64_t n, int nfeat, int nout, const double *X,
                          const double *target, int bf16, double *grad);
-void orc_project(const omech *m, double *dY);
+int orc_conserve(const omech *m, const double *Y0, double *Y1);
 int orc_surrogate_cell(const omech *m, const float *P, double p, double *T, double *Y, double dt,
                        double tau_T, double y_min, double margin);
 

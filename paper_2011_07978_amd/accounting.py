@@ -79,3 +79,19 @@ def state_bytes(mech) -> int:
     T, Y, h (FP64) plus status and step counters."""
     n = int(mech.n_species) + 1
     return 8 * (n + 2) + 8 * (n + 1) + 1 + 8
+
+
+BF16_MFMA_PEAK_TFLOPS = 2500.0   # dense bfloat16 matrix-core peak of MI355X
+
+
+def surrogate_flops_per_cell(n_species: int, hidden: int = 256, layers: int = 4) -> int:
+    """Multiply-adds of one surrogate forward pass on the unpadded widths
+    (N + 3 inputs, N + 1 outputs), an FMA counting 2."""
+    nin, nout = n_species + 3, n_species + 1
+    macs = nin * hidden + (layers - 1) * hidden * hidden + hidden * nout
+    return 2 * macs
+
+
+def surrogate_train_flops_per_sample(n_species: int) -> int:
+    """Forward, input-gradient and weight-gradient products: 3 x forward."""
+    return 3 * surrogate_flops_per_cell(n_species)

@@ -32,6 +32,15 @@ hipError_t launch_queue_build(int64_t ncells, const uint8_t *flags, const uint32
                               int *cursor, int *n_active, int *queue, hipStream_t s);
 hipError_t launch_ref_snapshot(int64_t ncells, int N, const double *T, const double *Y,
                                const int64_t *ref, double *snap, hipStream_t s);
+size_t big_lds_bytes(int n);
+hipError_t big_prepare(int n);
+int big_occupancy(int n);
+hipError_t launch_integrate_big(const MechDev &M, const MechDev *Md, const IntParams &P,
+                                int schedule, int grid, double *jws, hipStream_t s);
+hipError_t launch_big_rhs_jac(const MechDev &M, const MechDev *Md, const IntParams &P, double *f,
+                              double *J, hipStream_t s);
+hipError_t launch_big_rodas_step(const MechDev &M, const MechDev *Md, const IntParams &P, double h,
+                                 double *ynew, double *err, double *jws, hipStream_t s);
 hipError_t launch_map_scatter(int64_t ncells, int N, double *T, double *Y, const uint8_t *flags,
                               const int64_t *ref, const double *snap, double *delta,
                               const double *nasa_t, const double *invW, uint8_t *status,
@@ -70,6 +79,11 @@ struct chem_ctx {
                ev5 = nullptr;
     int64_t *d_refnone = nullptr;            // device -1: "no reference cell"
     int occ = 0;
+    // large mechanisms (n > 64): workgroup-per-cell kernel, Jacobian slots of
+    // the workgroups in flight
+    bool big = false;
+    double *d_jws = nullptr;
+    int big_slots = 0;
     bool in_capture = false, capture_failed = false;   // chem_graph_begin .. _end
     Surrogate *sur = nullptr;                // learned surrogate (null: not available)
     std::string sur_why;                     // why it is not available
@@ -113,7 +127,7 @@ void chem_default_options(chem_options *o) {
     o->order_by_cost = 1;
 }
 
-int chem_max_species(void) { return 63; }
+int chem_max_species(void) { return 137; }
 
 int chem_create(chem_ctx **out, int hip_device, void *hip_stream) {
     if (!out) return CHEM_E_INVALID_ARG;
@@ -154,6 +168,10 @@ static void free_mech(chem_ctx *c) {
     if (c->d_mapw) (void)hipFree(c->d_mapw);
     if (c->d_snap) (void)hipFree(c->d_snap);
     if (c->d_delta) (void)hipFree(c->d_delta);
+    if (c->d_jws) (void)hipFree(c->d_jws);
+    c->d_jws = nullptr;
+    c->big = false;
+    c->big_slots = 0;
     c->d_mapw = c->d_snap = c->d_delta = nullptr;
     c->d_mech = nullptr;
     delete c->sur;
@@ -221,8 +239,9 @@ static int upload(chem_ctx *c, const std::vector<T> &h, const T **dptr) {
     return CHEM_OK;
 }
 
-// Element-conservation projection data of the surrogate: E_ek = a_ek / W_k and
-// (E E^T)^-1 by Gauss-Jordan elimination with partial pivoting.
+// Element-conservation data of the surrogate: E_ek = a_ek / W_k.  E E^T must
+// be invertible (every element appears in some species); checked by
+// Gauss-Jordan elimination with partial pivoting.
 static int setup_surrogate(chem_ctx *c) {
     const int E = c->E, N = c->N;
     if (N > S_MAX_SPECIES) {
@@ -270,7 +289,7 @@ static int setup_surrogate(chem_ctx *c) {
     }
     Surrogate *sp = new Surrogate();
     char err[256] = {0};
-    if (sp->init(N, E, Em, Gi, err)) {
+    if (sp->init(N, E, Em, err)) {
         delete sp;
         return fail(c, CHEM_E_OOM, "surrogate: %s", err);
     }
@@ -448,6 +467,24 @@ int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
     c->NP = pick_np(M.n);
     c->occ = 0;
     if (c->NP > 0 && (size_t)M.lds_doubles * 8 <= 160 * 1024) c->occ = queue_occupancy(c->NP, M);
+    if (c->NP < 0) {
+        // workgroup-per-cell path: the iteration matrix must fit in one CU's LDS
+        int max_lds = 0;
+        HIPCHK(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
+        if (big_lds_bytes(M.n) <= (size_t)max_lds && big_prepare(M.n) == hipSuccess) {
+            const int occ = big_occupancy(M.n);
+            if (occ > 0) {
+                c->big = true;
+                c->occ = occ;
+                c->big_slots = c->num_cu * occ;
+                const size_t bytes = sizeof(double) * (size_t)M.n * M.n * c->big_slots;
+                if (hipMalloc((void **)&c->d_jws, bytes) != hipSuccess) {
+                    free_mech(c);
+                    return fail(c, CHEM_E_OOM, "hipMalloc Jacobian slots (%zu bytes)", bytes);
+                }
+            }
+        }
+    }
     if ((rc = setup_surrogate(c))) { free_mech(c); return rc; }
     c->has_mech = true;
     return CHEM_OK;
@@ -540,9 +577,10 @@ int chem_map_reference(chem_ctx *c, int64_t n, const double *T, const double *p,
 
 static int check_integrator(chem_ctx *c) {
     if (!c->has_mech) return fail(c, CHEM_E_NO_MECHANISM, "no mechanism");
+    if (c->big) return CHEM_OK;
     if (c->NP < 0)
-        return fail(c, CHEM_E_UNIMPL, "mechanisms with more than %d species are not supported by "
-                                      "the register-resident integrator", chem_max_species());
+        return fail(c, CHEM_E_UNIMPL, "%d species: the iteration matrix does not fit in one CU's "
+                                      "LDS", c->N);
     if ((size_t)c->M.lds_doubles * 8 > 160 * 1024)
         return fail(c, CHEM_E_UNIMPL, "mechanism tables exceed LDS (%d bytes)", c->M.lds_doubles * 8);
     return CHEM_OK;
@@ -596,6 +634,10 @@ static int integrate_core(chem_ctx *c, int64_t n, double *T, const double *p, do
         P.flags = flags;
         P.stats = c->d_stats;
         int grid = 0;
+        if (c->big) {
+            const int per_cu = c->opt.slots_per_cu > 0 ? std::min(c->opt.slots_per_cu, c->occ) : c->occ;
+            grid = (int)std::min<int64_t>(c->num_cu * per_cu, n);
+        }
         if (c->opt.schedule == CHEM_SCHED_QUEUE) {
             HIPCHK(c, launch_queue_build(n, flags, c->opt.order_by_cost ? cost : nullptr, hist, cursor,
                                          nact, c->d_queue, s));
@@ -603,12 +645,17 @@ static int integrate_core(chem_ctx *c, int64_t n, double *T, const double *p, do
             P.seg_ctr = seg;
             P.n_active = nact;
             P.chunk = c->opt.queue_chunk > 0 ? c->opt.queue_chunk : 1;
-            const int slots = c->opt.slots_per_cu > 0 ? c->opt.slots_per_cu : std::max(1, c->occ);
-            grid = c->num_cu * slots;
-            if (grid > n) grid = (int)n;
+            if (!c->big) {
+                const int slots = c->opt.slots_per_cu > 0 ? c->opt.slots_per_cu : std::max(1, c->occ);
+                grid = c->num_cu * slots;
+                if (grid > n) grid = (int)n;
+            }
         }
         if (stats) HIPCHK(c, hipEventRecord(c->ev2, s));
-        HIPCHK(c, launch_integrate(c->NP, c->M, c->d_mech, P, c->opt.schedule, grid, s));
+        if (c->big)
+            HIPCHK(c, launch_integrate_big(c->M, c->d_mech, P, c->opt.schedule, grid, c->d_jws, s));
+        else
+            HIPCHK(c, launch_integrate(c->NP, c->M, c->d_mech, P, c->opt.schedule, grid, s));
         if (stats) HIPCHK(c, hipEventRecord(c->ev3, s));
         if (flags)
             HIPCHK(c, launch_map_scatter(n, c->N, T, Y, flags, ref_index, c->d_snap, c->d_delta,
@@ -817,7 +864,8 @@ int chem_eval_rhs_jac(chem_ctx *c, int64_t n, const double *T, const double *p, 
     IntParams P{};
     P.ncells = n;
     P.T = const_cast<double *>(T); P.p = p; P.Y = const_cast<double *>(Y);
-    HIPCHK(c, launch_eval_rhs_jac(c->NP, c->M, c->d_mech, P, f, J, c->stream));
+    if (c->big) HIPCHK(c, launch_big_rhs_jac(c->M, c->d_mech, P, f, J, c->stream));
+    else HIPCHK(c, launch_eval_rhs_jac(c->NP, c->M, c->d_mech, P, f, J, c->stream));
     return CHEM_OK;
 }
 
@@ -832,6 +880,19 @@ int chem_rodas_step(chem_ctx *c, int64_t n, const double *T, const double *p, co
     IntParams P{};
     P.ncells = n;
     P.T = const_cast<double *>(T); P.p = p; P.Y = const_cast<double *>(Y);
+    if (c->big) {
+        // one Jacobian slot per cell for this check
+        if (capturing(c)) return fail(c, CHEM_E_CAPTURE_UNSAFE, "chem_rodas_step allocates here");
+        double *jws = nullptr;
+        const size_t bytes = sizeof(double) * (size_t)c->M.n * c->M.n * (size_t)n;
+        if (hipMalloc((void **)&jws, bytes) != hipSuccess)
+            return fail(c, CHEM_E_OOM, "hipMalloc Jacobian slots (%zu bytes)", bytes);
+        hipError_t e = launch_big_rodas_step(c->M, c->d_mech, P, h, ynew, err, jws, c->stream);
+        if (e == hipSuccess) e = c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize();
+        (void)hipFree(jws);
+        if (e != hipSuccess) return fail(c, CHEM_E_HIP, "big rodas step: %s", hipGetErrorString(e));
+        return CHEM_OK;
+    }
     HIPCHK(c, launch_rodas_step(c->NP, c->M, c->d_mech, P, h, ynew, err, c->stream));
     return CHEM_OK;
 }

@@ -1,13 +1,14 @@
 // Learned surrogate for the per-cell dt-advance: BF16-MFMA MLP training and
-// inference, element-conservation projection and acceptance gate.
+// inference, element conservation and acceptance gate.
 //
-// Network (shared definition with the oracle): features
-//   x = (ln T, ln p, Y_1..Y_N, ln dt), normalised and padded to 64,
-// four hidden layers of 256 with GELU (erf form), output 64 (first N+1 used:
-// normalised dY_1..dY_N, dT).  Weights and activations are bfloat16, products
-// accumulate in FP32 on the matrix cores (v_mfma_f32_16x16x32_bf16), biases and
-// GELU in FP32.  Training: mean-squared error on the normalised outputs, Adam
-// on FP32 master weights.
+// Network: features x = (ln T, ln p, Y_1..Y_N, ln dt), normalised and padded
+// to 64, four hidden layers of 256 with GELU (erf form), output 64 of which
+// the first N+1 are the normalised increments in an inverse hyperbolic-sine
+// scale: t = o sd_o + mu_o, dY_k = S_Y sinh(t_k), dT = S_T sinh(t_N).
+// Weights and activations are bfloat16, products accumulate in FP32 on the
+// matrix cores (v_mfma_f32_16x16x32_bf16), biases and GELU in FP32.
+// Training: mean-squared error on the normalised outputs, Adam on FP32 master
+// weights.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -155,10 +156,12 @@ __global__ __launch_bounds__(256) void k_feature_moments(FeatSrc f, int ncol, do
     }
 }
 
-// targets: dY_k = Y1_k - Y0_k (k < N), dT = T1 - T0
+// targets: the increments dY_k = Y1_k - Y0_k (k < N) and dT = T1 - T0
+// Increments in the network's output scale: asinh(dY_k / S_Y), asinh(dT / S_T).
+constexpr double S_Y = 1e-12, S_T = 1e-6;
 __device__ __forceinline__ double raw_target(const TgtSrc &t, int64_t i, int c) {
-    if (c < t.N) return t.Y1[(int64_t)c * t.n + i] - t.Y0[(int64_t)c * t.n + i];
-    return t.T1[i] - t.T0[i];
+    if (c < t.N) return asinh((t.Y1[(int64_t)c * t.n + i] - t.Y0[(int64_t)c * t.n + i]) / S_Y);
+    return asinh((t.T1[i] - t.T0[i]) / S_T);
 }
 __global__ __launch_bounds__(256) void k_target_moments(TgtSrc t, double *out) {
     const int c = blockIdx.x;
@@ -273,20 +276,29 @@ __global__ __launch_bounds__(256) void k_refresh(const float *W, int no, int ni,
     WbT[(size_t)i * no + o] = b;
 }
 
-// ------------------------------------------------------ projection + gate ----
+// ------------------------------------------------- conservation + gate ----
 struct PostParams {
     int N, nel;
     const double *E;       // [nel][N] a_ek / W_k
-    const double *Ginv;    // [nel][nel] (E E^T)^-1
-    const double *nasa_t;  // species thermo (a1..a7, a2/2, a3/3, a4/4, a5/5, ...)
+    const double *nasa_t;  // species thermo [14][N] (a1..a7, a2/2, a3/3, a4/4, a5/5, ...)
     const double *invW;
     const float *norm;     // mu_x, sd_x, mu_o, sd_o, xmin, xmax
     double tau_T, y_min, margin;
 };
 
+__device__ __forceinline__ double pred_y(const PostParams &q, const float *outT, int m, int r, int k,
+                                         double yk) {
+    const double t = (double)outT[(size_t)k * m + r] * q.norm[192 + k] + q.norm[128 + k];
+    const double v = yk + S_Y * sinh(t);
+    return v > 0.0 ? v : 0.0;
+}
+
 // One cell per thread.  outT [64][m] normalised network outputs of chunk
-// rows; row r is cell base + r.  Accepted cells get Y' = Y + P dY, T from
-// enthalpy conservation, flag 3; rejected cells are left untouched.
+// rows; row r is cell base + r.  The clipped prediction Y1 = max(Y + dY, 0)
+// is corrected by Y1_k (E^T lam)_k with (E W E^T) lam = E (Y1 - Y), W =
+// diag(Y1); T' solves h(T', Y') = h(T, Y).  Accepted cells are updated and
+// flagged 3; rejected cells are left untouched.
+template <int NEL>
 __global__ __launch_bounds__(256) void k_surrogate_post(FeatSrc f, int64_t base, int m,
                                                         const float *outT, PostParams q, double *T,
                                                         double *Y, uint8_t *flags,
@@ -306,35 +318,87 @@ __global__ __launch_bounds__(256) void k_surrogate_post(FeatSrc f, int64_t base,
                 const double span = hi - lo;
                 ok = v >= lo - q.margin * span && v <= hi + q.margin * span;
             }
-            double lam[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            double dT = 0.0, Tn = 0.0;
+            double lam[NEL];
+            double Tn = 0.0, dT = 0.0;
             if (ok) {
-                double rr[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                double G[NEL][NEL], rr[NEL];
+#pragma unroll
+                for (int a = 0; a < NEL; ++a) {
+                    rr[a] = 0.0;
+#pragma unroll
+                    for (int b = 0; b < NEL; ++b) G[a][b] = 0.0;
+                }
                 for (int k = 0; k < N; ++k) {
-                    const double d = (double)outT[(size_t)k * m + r] * q.norm[192 + k] + q.norm[128 + k];
-                    for (int e = 0; e < q.nel; ++e) rr[e] += q.E[e * N + k] * d;
+                    const double y0 = Y[(int64_t)k * f.n + i];
+                    const double y1 = pred_y(q, outT, m, r, k, y0);
+                    double ek[NEL];
+#pragma unroll
+                    for (int a = 0; a < NEL; ++a) ek[a] = q.E[a * N + k];
+#pragma unroll
+                    for (int a = 0; a < NEL; ++a) {
+                        rr[a] += ek[a] * (y1 - y0);
+#pragma unroll
+                        for (int b = 0; b < NEL; ++b) G[a][b] += ek[a] * y1 * ek[b];
+                    }
                 }
-                for (int a = 0; a < q.nel; ++a) {
-                    double s = 0.0;
-                    for (int b = 0; b < q.nel; ++b) s += q.Ginv[a * q.nel + b] * rr[b];
-                    lam[a] = s;
+                // Gaussian elimination with partial pivoting
+#pragma unroll
+                for (int c = 0; c < NEL; ++c) {
+                    int pr = c;
+#pragma unroll
+                    for (int a = c + 1; a < NEL; ++a)
+                        if (fabs(G[a][c]) > fabs(G[pr][c])) pr = a;
+#pragma unroll
+                    for (int a = c + 1; a < NEL; ++a) {
+                        if (a == pr) {
+#pragma unroll
+                            for (int b = 0; b < NEL; ++b) {
+                                const double t0 = G[c][b];
+                                G[c][b] = G[a][b];
+                                G[a][b] = t0;
+                            }
+                            const double t1 = rr[c];
+                            rr[c] = rr[a];
+                            rr[a] = t1;
+                        }
+                    }
+                    ok = ok && G[c][c] != 0.0;
+                    const double dinv = 1.0 / G[c][c];
+#pragma unroll
+                    for (int a = c + 1; a < NEL; ++a) {
+                        const double l = G[a][c] * dinv;
+#pragma unroll
+                        for (int b = c; b < NEL; ++b) G[a][b] -= l * G[c][b];
+                        rr[a] -= l * rr[c];
+                    }
                 }
-                dT = (double)outT[(size_t)N * m + r] * q.norm[192 + N] + q.norm[128 + N];
-                // projected increments: positivity and the enthalpy polynomial
+#pragma unroll
+                for (int c = NEL - 1; c >= 0; --c) {
+                    double s = rr[c];
+#pragma unroll
+                    for (int b = c + 1; b < NEL; ++b) s -= G[c][b] * lam[b];
+                    lam[c] = s / G[c][c];
+                }
+#pragma unroll
+                for (int a = 0; a < NEL; ++a) ok = ok && isfinite(lam[a]);
+                dT = S_T * sinh((double)outT[(size_t)N * m + r] * q.norm[192 + N] + q.norm[128 + N]);
+                // corrected state: positivity gate and the enthalpy polynomial
                 double Bo[6] = {0, 0, 0, 0, 0, 0}, Bn[6] = {0, 0, 0, 0, 0, 0};
                 for (int k = 0; k < N && ok; ++k) {
-                    double d = (double)outT[(size_t)k * m + r] * q.norm[192 + k] + q.norm[128 + k];
-                    for (int e = 0; e < q.nel; ++e) d -= q.E[e * N + k] * lam[e];
-                    const double yo = Y[(int64_t)k * f.n + i];
-                    const double yn = yo + d;
+                    const double y0 = Y[(int64_t)k * f.n + i];
+                    const double y1 = pred_y(q, outT, m, r, k, y0);
+                    double s = 0.0;
+#pragma unroll
+                    for (int a = 0; a < NEL; ++a) s += q.E[a * N + k] * lam[a];
+                    const double yn = y1 - y1 * s;
                     ok = yn >= q.y_min;
                     const double iw = q.invW[k];
                     const double c6[6] = {q.nasa_t[k], q.nasa_t[7 * N + k], q.nasa_t[8 * N + k],
                                           q.nasa_t[9 * N + k], q.nasa_t[10 * N + k], q.nasa_t[5 * N + k]};
 #pragma unroll
-                    for (int s = 0; s < 6; ++s) {
-                        Bo[s] += yo * iw * c6[s];
-                        Bn[s] += yn * iw * c6[s];
+                    for (int t = 0; t < 6; ++t) {
+                        Bo[t] += y0 * iw * c6[t];
+                        Bn[t] += yn * iw * c6[t];
                     }
                 }
                 if (ok) {
@@ -353,9 +417,12 @@ __global__ __launch_bounds__(256) void k_surrogate_post(FeatSrc f, int64_t base,
             }
             if (ok) {
                 for (int k = 0; k < N; ++k) {
-                    double d = (double)outT[(size_t)k * m + r] * q.norm[192 + k] + q.norm[128 + k];
-                    for (int e = 0; e < q.nel; ++e) d -= q.E[e * N + k] * lam[e];
-                    Y[(int64_t)k * f.n + i] += d;
+                    double *yp = Y + (int64_t)k * f.n + i;
+                    const double y1 = pred_y(q, outT, m, r, k, *yp);
+                    double s = 0.0;
+#pragma unroll
+                    for (int a = 0; a < NEL; ++a) s += q.E[a * N + k] * lam[a];
+                    *yp = y1 - y1 * s;
                 }
                 T[i] = Tn;
                 if (flags) flags[i] = 3;
@@ -367,6 +434,20 @@ __global__ __launch_bounds__(256) void k_surrogate_post(FeatSrc f, int64_t base,
     if ((threadIdx.x & 63) == 0) {
         if (na) atomicAdd(&stats[6], (unsigned long long)__popcll(na));
         if (nt & ~na) atomicAdd(&stats[7], (unsigned long long)__popcll(nt & ~na));
+    }
+}
+
+static void launch_post(int nel, dim3 g, hipStream_t s, const FeatSrc &f, int64_t base, int m,
+                        const float *outT, const PostParams &q, double *T, double *Y, uint8_t *flags,
+                        unsigned long long *stats) {
+    switch (nel) {
+#define POST(E_)                                                                                   \
+    case E_:                                                                                       \
+        hipLaunchKernelGGL(k_surrogate_post<E_>, g, dim3(256), 0, s, f, base, m, outT, q, T, Y,   \
+                           flags, stats);                                                          \
+        break;
+        POST(1) POST(2) POST(3) POST(4) POST(5) POST(6) POST(7) POST(8)
+#undef POST
     }
 }
 
@@ -405,8 +486,7 @@ Surrogate::~Surrogate() {
     for (void *p : ws) (void)hipFree(p);
 }
 
-int Surrogate::init(int N_, int nel_, const std::vector<double> &E_host,
-                    const std::vector<double> &Ginv_host, char *err) {
+int Surrogate::init(int N_, int nel_, const std::vector<double> &E_host, char *err) {
     N = N_;
     nel = nel_;
     const int64_t np = surrogate_param_count();
@@ -423,8 +503,6 @@ int Surrogate::init(int N_, int nel_, const std::vector<double> &E_host,
     double *dp = nullptr;
     SCHK(dalloc(&dp, E_host.size())); bufs.push_back(dp); E = dp;
     SCHK(hipMemcpy(E, E_host.data(), sizeof(double) * E_host.size(), hipMemcpyHostToDevice));
-    SCHK(dalloc(&dp, Ginv_host.size())); bufs.push_back(dp); Ginv = dp;
-    SCHK(hipMemcpy(Ginv, Ginv_host.data(), sizeof(double) * Ginv_host.size(), hipMemcpyHostToDevice));
     SCHK(dalloc(&dp, 1)); bufs.push_back(dp); d_loss = dp;
     return 0;
 }
@@ -700,7 +778,7 @@ int Surrogate::apply(const FeatSrc &f, double *T, double *Y, uint8_t *flags, con
     int rc = reserve_ws((int)std::min<int64_t>(n, chunk), false, err);
     if (rc) return rc;
     PostParams q{};
-    q.N = N; q.nel = nel; q.E = E; q.Ginv = Ginv; q.nasa_t = pin.nasa_t; q.invW = pin.invW;
+    q.N = N; q.nel = nel; q.E = E; q.nasa_t = pin.nasa_t; q.invW = pin.invW;
     q.norm = P + weights_count(); q.tau_T = pin.tau_T; q.y_min = pin.y_min; q.margin = pin.margin;
     TgtSrc t{};
     for (int64_t base = 0; base < n; base += chunk) {
@@ -708,8 +786,7 @@ int Surrogate::apply(const FeatSrc &f, double *T, double *Y, uint8_t *flags, con
         hipLaunchKernelGGL(k_build_rows, dim3((m + 3) / 4), dim3(256), 0, s, f, t, (const int *)nullptr,
                            base, m, P + weights_count(), X, (uint16_t *)nullptr, 0, (float *)nullptr);
         forward(m, false, true, s);
-        hipLaunchKernelGGL(k_surrogate_post, dim3((m + 255) / 256), dim3(256), 0, s, f, base, m, out, q, T,
-                           Y, flags, stats);
+        launch_post(nel, dim3((m + 255) / 256), s, f, base, m, out, q, T, Y, flags, stats);
     }
     SCHK(hipGetLastError());
     return 0;

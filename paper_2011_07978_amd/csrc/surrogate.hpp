@@ -43,8 +43,8 @@ struct Surrogate {
     // Adam moments; bf16 copies of every weight matrix and of its transpose
     float *P = nullptr, *G = nullptr, *mA = nullptr, *vA = nullptr;
     uint16_t *Wb[5] = {}, *WbT[5] = {};
-    // element-conservation projection: E [nel][N] = a_ek / W_k, (E E^T)^-1
-    double *E = nullptr, *Ginv = nullptr;
+    // element conservation: E [nel][N] = a_ek / W_k
+    double *E = nullptr;
     double *d_loss = nullptr;
     std::vector<void *> bufs;
     // row workspace
@@ -57,8 +57,7 @@ struct Surrogate {
     int *idx = nullptr;
 
     ~Surrogate();
-    int init(int N, int nel, const std::vector<double> &E_host, const std::vector<double> &Ginv_host,
-             char *err);
+    int init(int N, int nel, const std::vector<double> &E_host, char *err);
     int refresh(hipStream_t s, char *err);
     int set_params(const float *host, hipStream_t s, char *err);
     int get_params(float *host, hipStream_t s, char *err);

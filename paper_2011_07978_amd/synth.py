@@ -398,18 +398,19 @@ SUR_DIMS = (64, 256, 256, 256, 256, 64)   # padded layer widths of the surrogate
 
 
 def surrogate_params(n_species: int, seed: int = 0, weight_scale: float = 1.0,
-                     dY_scale: float = 1e-4, dT_scale: float = 10.0, zero_output_weights=False,
+                     out_sd=(4.0, 4.0), zero_output_weights=False, out_bias=None,
                      box=None) -> np.ndarray:
     """Seeded float32 parameter blob in the surrogate's layout, for tests.
 
     Layer l: W [out x in] ~ N(0, weight_scale^2 / in) on the live rows and
     columns (n_species + 3 inputs, n_species + 1 outputs), zero on the padding;
     b ~ N(0, 0.1^2) on live outputs.  zero_output_weights makes the output
-    layer's W zero, so the network output equals its bias exactly.
-    Normalisation: features centred on (ln 1000 K, ln 1 atm, 0.02, ln 1e-6 s)
-    with spreads (0.5, 1, 0.1, 1); outputs scaled by dY_scale per species and
-    dT_scale for T.  box = (xmin, xmax) arrays of the N + 3 live features, or
-    None for an unbounded box."""
+    layer's W zero, so the network output equals its bias exactly; out_bias
+    (n_species + 1 values) replaces that bias.  Normalisation: features
+    centred on (ln 1000 K, ln 1 atm, 0.02, ln 1e-6 s) with spreads
+    (0.5, 1, 0.1, 1); outputs with mean 0 and spreads out_sd = (species, T).
+    box = (xmin, xmax) arrays of the N + 3 live features, or None for an
+    unbounded box."""
     N = int(n_species)
     rng = _rng(seed)
     nfeat, nout = N + 3, N + 1
@@ -423,6 +424,8 @@ def surrogate_params(n_species: int, seed: int = 0, weight_scale: float = 1.0,
         if not (l == 4 and zero_output_weights):
             W[:live_o, :live_i] = rng.standard_normal((live_o, live_i)) * weight_scale / np.sqrt(ni)
         b[:live_o] = rng.standard_normal(live_o) * 0.1
+        if l == 4 and out_bias is not None:
+            b[:nout] = out_bias
         blob += [W.ravel(), b]
     mu_x = np.zeros(64)
     sd_x = np.ones(64)
@@ -432,8 +435,8 @@ def surrogate_params(n_species: int, seed: int = 0, weight_scale: float = 1.0,
     mu_x[2 + N], sd_x[2 + N] = np.log(1e-6), 1.0
     mu_o = np.zeros(64)
     sd_o = np.ones(64)
-    sd_o[:N] = dY_scale
-    sd_o[N] = dT_scale
+    sd_o[:N] = out_sd[0]
+    sd_o[N] = out_sd[1]
     xmin = np.full(64, -1e30)
     xmax = np.full(64, 1e30)
     if box is not None:
@@ -441,6 +444,17 @@ def surrogate_params(n_species: int, seed: int = 0, weight_scale: float = 1.0,
         xmax[:nfeat] = box[1]
     blob += [mu_x, sd_x, mu_o, sd_o, xmin, xmax]
     return np.concatenate(blob).astype(np.float32)
+
+
+def surrogate_increment_bias(n_species: int, seed: int, dY_sd: float, dT_sd: float) -> np.ndarray:
+    """Output-layer bias that, with zero output weights and unit output
+    spreads, makes the network predict fixed increments dY ~ N(0, dY_sd^2) per
+    species and dT ~ N(0, dT_sd^2): the increments in the output scale,
+    asinh(dY / 1e-12) and asinh(dT / 1e-6 K)."""
+    rng = _rng(seed)
+    dY = rng.standard_normal(n_species) * dY_sd
+    dT = rng.standard_normal() * dT_sd
+    return np.r_[np.arcsinh(dY / 1e-12), np.arcsinh(dT / 1e-6)]
 
 
 def surrogate_pairs_field(n_cells: int, seed: int = 900) -> Field:

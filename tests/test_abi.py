@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_no_compute_without_context():
     L = chem.load_library()
-    assert L.chem_max_species() == 63
+    assert L.chem_max_species() == 137
     o = chem.Options()
     L.chem_default_options(ctypes.byref(o))
     assert o.rtol == 1e-8 and o.atol == 1e-12 and o.schedule == chem.CHEM_SCHED_QUEUE

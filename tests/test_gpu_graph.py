@@ -44,8 +44,9 @@ def test_graph_of_ten_steps_replays_bitwise(surrogate):
     mech = synth.mechanism("mech53")
     f = synth.field_mapped(6000, seed=81)
     n_steps = 10 if not surrogate else 3
-    P = synth.surrogate_params(mech.n_species, seed=82, zero_output_weights=True, dY_scale=1e-8,
-                               dT_scale=0.01) if surrogate else None
+    P = synth.surrogate_params(mech.n_species, seed=82, zero_output_weights=True, out_sd=(1.0, 1.0),
+                               out_bias=synth.surrogate_increment_bias(mech.n_species, 83, 1e-8, 0.01)
+                               ) if surrogate else None
     stream = torch.cuda.Stream()
     keys = ("T", "Y", "h", "cost", "flags", "status")
     say("graph eager reference, surrogate", surrogate)

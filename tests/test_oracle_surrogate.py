@@ -100,22 +100,33 @@ def test_backprop_matches_central_differences():
     assert np.all(g[nparam:] == 0)
 
 
-def test_projection_properties():
+def test_conservation_of_clipped_prediction():
     mech = synth.mechanism("mech53")
     o = Oracle(mech)
+    N = mech.n_species
     E = (mech.composition.T / mech.W[None, :])          # [elements, species]
     rng = np.random.default_rng(8)
-    for _ in range(5):
-        dY = rng.standard_normal(mech.n_species) * 1e-3
-        d1 = oracle.project(o, dY)
-        assert np.abs(E @ d1).max() <= 1e-15 * np.abs(E).max() * np.abs(dY).max() * 100
-        assert abs(d1.sum()) <= 1e-15
-        np.testing.assert_allclose(oracle.project(o, d1), d1, atol=1e-19)      # idempotent
-        # the correction lies in the row space of E (minimum-norm projection)
-        corr = dY - d1
-        lam, *_ = np.linalg.lstsq(E.T, corr, rcond=None)
-        np.testing.assert_allclose(E.T @ lam, corr, atol=1e-17)
-        assert np.linalg.norm(d1) <= np.linalg.norm(dY)
+    f = synth.field_mapped(400, seed=9)
+    for i in range(0, 400, 40):
+        Y0 = f.Y[:, i]
+        Y1 = np.maximum(Y0 + rng.standard_normal(N) * 1e-4, 0.0)
+        Y2 = oracle.conserve(o, Y0, Y1)
+        scale = np.abs(E).max() * 1e-3
+        assert np.abs(E @ (Y2 - Y0)).max() <= 1e-14 * scale * 100
+        assert abs((Y2 - Y0).sum()) <= 1e-15
+        assert np.all(Y2[Y1 == 0.0] == 0.0)              # clipped species stay at zero
+        # the correction is Y1_k (E^T lam)_k: weighted minimum norm
+        pos = Y1 > 0
+        d = (Y1 - Y2)[pos] / Y1[pos]
+        lam, *_ = np.linalg.lstsq(E.T[pos], d, rcond=None)
+        np.testing.assert_allclose(E.T[pos] @ lam, d, atol=1e-12 * max(1.0, np.abs(d).max()))
+        # idempotent
+        np.testing.assert_allclose(oracle.conserve(o, Y0, Y2), Y2, rtol=0, atol=1e-15)
+    # a uniform rescaling is undone exactly: the correction (c - 1) / c is the
+    # constant vector E^T (m_e (c - 1) / c), m_e the element masses
+    Y0 = f.Y[:, 7]
+    for c in (0.9, 1.05, 1.3):
+        np.testing.assert_allclose(oracle.conserve(o, Y0, c * Y0), Y0, rtol=1e-13, atol=1e-19)
 
 
 def test_surrogate_cell_gate_and_conservation():
