@@ -145,7 +145,8 @@ def train_surrogate(chem, mech, args, torch, accounting):
     t_train = time.perf_counter() - t0
     log(f"surrogate: {pairs.n} pairs in {t_pairs:.1f} s, {args.sur_epochs} epochs in {t_train:.1f} s, "
         f"loss {hist[0]:.3e} -> {hist[-1]:.3e}")
-    val = surrogate.validate(chem, va, gate=dict(tau_T=args.tau_T))
+    val = surrogate.validate(chem, va, gate=dict(tau_T=args.tau_T, margin=args.margin,
+                                                 max_dT=args.max_dT))
     fl = accounting.surrogate_train_flops_per_sample(mech.n_species) * tr.n * args.sur_epochs
     return dict(pairs=pairs.n, train_pairs=tr.n, validation_pairs=va.n, epochs=args.sur_epochs,
                 seconds_pairs=t_pairs, seconds_train=t_train,
@@ -201,6 +202,20 @@ def first_step_error(mech, field, synth, rec, idx, threads):
     a = acc
     out["surrogate_cells_mean_abs_dT"] = float(dT[a].mean()) if a.any() else None
     out["surrogate_cells_max_abs_dT"] = float(dT[a].max()) if a.any() else None
+    return out
+
+
+def trajectory_drift(field, S_sur, S_fp64, n_steps):
+    """The two paths advanced the same field for the same steps: the state
+    difference accumulates every surrogate step's error."""
+    dT = (S_sur["T"] - S_fp64["T"]).abs().cpu().numpy()
+    out = dict(flow_steps=n_steps, mean_abs_dT=float(dT.mean()), max_abs_dT=float(dT.max()),
+               by_class={})
+    for c, name in enumerate(field.class_names):
+        sel = field.cls == c
+        if sel.any():
+            out["by_class"][name] = dict(mean_abs_dT=float(dT[sel].mean()),
+                                         max_abs_dT=float(dT[sel].max()))
     return out
 
 
@@ -285,6 +300,8 @@ def main():
     ap.add_argument("--sur-steps", type=int, default=8, help="flow steps of the pair field")
     ap.add_argument("--sur-epochs", type=int, default=8)
     ap.add_argument("--tau-T", type=float, default=0.5)
+    ap.add_argument("--margin", type=float, default=0.01, help="gate: training-box margin")
+    ap.add_argument("--max-dT", type=float, default=1.0, help="gate: largest predicted |dT| (K)")
     ap.add_argument("--graph", action="store_true",
                     help="also time the balanced steps recorded into one HIP graph")
     ap.add_argument("--autotune", action="store_true",
@@ -313,7 +330,7 @@ def main():
     threads = min(16, os.cpu_count() or 1)
 
     sur = None
-    gate = dict(tau_T=args.tau_T, y_min=-1e-10, margin=0.0)
+    gate = dict(tau_T=args.tau_T, y_min=-1e-10, margin=args.margin, max_dT=args.max_dT)
     if use_sur:
         sur = train_surrogate(chem, mech, args, torch, accounting)
     chem.reserve(field.n_cells)
@@ -339,6 +356,7 @@ def main():
                                       synth)
         balanced = dict(value=field.n_cells / (ms_b / 1e3), ms_per_step=ms_b,
                         integrate_ms=float(np.mean([s["ms_integrate"] for s in st_b])))
+        sur["drift_vs_fp64_path"] = trajectory_drift(field, S_h, S_b, args.warmup + args.steps)
         sur["steady_state_vs_fp64_path"] = steady_state_error(chem, S_h, torch, S_h["one_step"],
                                                               S_b["one_step"])
         del S_b
@@ -394,7 +412,8 @@ def main():
 
     desc = (f"{args.workload}: {field.n_cells} cells, {mech.n_species} species / "
             f"{mech.n_reactions} reactions, dt {field.dt} s, rtol 1e-8, atol 1e-12, map (Z_tol 1e-4)"
-            + (" + BF16 MLP surrogate with conservation and gate (tau_T %g K)" % args.tau_T
+            + (" + BF16 MLP surrogate with conservation and gate (tau_T %g K, max |dT| %g K)"
+               % (args.tau_T, args.max_dT)
                if use_sur else "")
             + " + heavy-first queue + Rodas4 + mapped update")
     out = {

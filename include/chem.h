@@ -159,8 +159,8 @@ typedef struct {
  * to each species' mass fraction).  T' solves h(T', Y') = h(T, Y).  The gate
  * (chem_gate_params) sends a cell back to the Rosenbrock solver unless every
  * raw feature lies in [xmin - margin*(xmax - xmin), xmax + margin*(xmax -
- * xmin)], E diag(Y1) E^T is invertible, every Y'_k >= y_min and
- * |T + dT - T'| <= tau_T.
+ * xmin)], |dT| <= max_dT, E diag(Y1) E^T is invertible, every Y'_k >= y_min
+ * and |T + dT - T'| <= tau_T.
  * Available for N <= 61 species and E <= 8 elements with E E^T invertible
  * (otherwise the surrogate entry points return CHEM_E_UNIMPL). */
 typedef struct {
@@ -175,7 +175,14 @@ typedef struct {
 typedef struct {
     double tau_T;         /* K (default 0.5) */
     double y_min;         /* (default -1e-10) */
-    double margin;        /* fraction of each feature's training span (default 0) */
+    double margin;        /* fraction of each feature's training span (default 0.01: a
+                             species the conservation step clipped to zero sits
+                             just below the training minimum, and must not send
+                             the cell back to the solver next step) */
+    double max_dT;        /* K: cells whose predicted |dT| exceeds it go to the
+                             solver (default 1: the surrogate takes slowly
+                             changing cells; igniting cells stay on the FP64
+                             path) */
 } chem_gate_params;
 
 /* Create a context on HIP device `hip_device`, enqueueing on `hip_stream`
@@ -245,7 +252,9 @@ int chem_integrate(chem_ctx *ctx, int64_t n_cells, double *T, const double *p, d
  * updated in place and flagged CHEM_FLAG_SURROGATE (flags is device in/out
  * and required; zero-fill it when no mapping is used), all other cells are
  * handled as by chem_integrate.  ref_index may be NULL when no flag is 1 or 2.
- * Status CHEM_CELL_SURROGATE marks surrogate cells.  Requires parameters
+ * Status CHEM_CELL_SURROGATE marks surrogate cells; their cost entry is set
+ * to 0x7fffffff (unknown), which queues them first should a later call send
+ * them to the solver.  Requires parameters
  * (chem_surrogate_train, _set_params or _load).  With a warm workspace (a
  * previous call with at least min(n, 262144) cells) it allocates nothing. */
 int chem_integrate_surrogate(chem_ctx *ctx, int64_t n_cells, double *T, const double *p, double *Y,

@@ -232,9 +232,12 @@ int orc_conserve(const omech *m, const double *Y0, double *Y1)
 }
 
 /* One surrogate step for one cell (raw state in/out); returns 1 if the gate
- * accepts (state updated), 0 if the cell must go to the Rosenbrock solver. */
+ * accepts (state updated), 0 if the cell must go to the Rosenbrock solver.
+ * Gate: every raw feature inside the training box widened by margin times its
+ * span, |dT| <= max_dT, E diag(Y1) E^T invertible, Y' >= y_min,
+ * |T + dT - T'| <= tau_T. */
 int orc_surrogate_cell(const omech *m, const float *P, double p, double *T, double *Y, double dt,
-                       double tau_T, double y_min, double margin)
+                       double tau_T, double y_min, double margin, double max_dT)
 {
     const int N = m->N;
     const float *nb = norm_block(P);
@@ -253,6 +256,7 @@ int orc_surrogate_cell(const omech *m, const float *P, double p, double *T, doub
         Yn[k] = yk > 0.0 ? yk : 0.0;
     }
     const double dT = S_T * sinh(out[N] * sd_o[N] + mu_o[N]);
+    if (!(fabs(dT) <= max_dT)) return 0;
     if (orc_conserve(m, Y, Yn) != 0) return 0;
     for (int k = 0; k < N; ++k)
         if (!(Yn[k] >= y_min)) return 0;

@@ -44,7 +44,7 @@ hipError_t launch_big_rodas_step(const MechDev &M, const MechDev *Md, const IntP
 hipError_t launch_map_scatter(int64_t ncells, int N, double *T, double *Y, const uint8_t *flags,
                               const int64_t *ref, const double *snap, double *delta,
                               const double *nasa_t, const double *invW, uint8_t *status,
-                              unsigned long long *stats, hipStream_t s);
+                              uint32_t *cost, unsigned long long *stats, hipStream_t s);
 }  // namespace chem
 
 using namespace chem;
@@ -616,7 +616,7 @@ static int integrate_core(chem_ctx *c, int64_t n, double *T, const double *p, do
         if (gate) {
             if (stats) HIPCHK(c, hipEventRecord(c->ev4, s));
             FeatSrc f{T, p, Y, nullptr, dt, n, c->N};
-            PostIn pin{c->M.nasa_t, c->M.invW, gate->tau_T, gate->y_min, gate->margin};
+            PostIn pin{c->M.nasa_t, c->M.invW, gate->tau_T, gate->y_min, gate->margin, gate->max_dT};
             char err[256] = {0};
             if (c->sur->apply(f, T, Y, flags, pin, c->d_stats, s, err))
                 return fail(c, CHEM_E_HIP, "surrogate: %s", err);
@@ -659,7 +659,7 @@ static int integrate_core(chem_ctx *c, int64_t n, double *T, const double *p, do
         if (stats) HIPCHK(c, hipEventRecord(c->ev3, s));
         if (flags)
             HIPCHK(c, launch_map_scatter(n, c->N, T, Y, flags, ref_index, c->d_snap, c->d_delta,
-                                         c->M.nasa_t, c->M.invW, status, c->d_stats, s));
+                                         c->M.nasa_t, c->M.invW, status, cost, c->d_stats, s));
     }
     if (!stats) return CHEM_OK;
     HIPCHK(c, hipEventRecord(c->ev1, s));
@@ -705,7 +705,8 @@ int chem_integrate_surrogate(chem_ctx *c, int64_t n, double *T, const double *p,
     if (n < 0 || n > (int64_t)INT32_MAX || !(dt > 0.0) || !isfinite(dt) || !gate)
         return fail(c, CHEM_E_INVALID_ARG, "chem_integrate_surrogate: bad n, dt or gate");
     if (n > 0 && (!T || !p || !Y || !flags)) return fail(c, CHEM_E_INVALID_ARG, "null state or flags array");
-    if (!(gate->tau_T >= 0.0) || !(gate->margin >= 0.0) || gate->y_min != gate->y_min)
+    if (!(gate->tau_T >= 0.0) || !(gate->margin >= 0.0) || gate->y_min != gate->y_min ||
+        !(gate->max_dT >= 0.0))
         return fail(c, CHEM_E_INVALID_ARG, "bad gate parameters");
     return integrate_core(c, n, T, p, Y, dt, flags, ref_index, h, cost, status, steps, stats, gate);
 }
@@ -723,7 +724,8 @@ void chem_default_train_params(chem_train_params *t) {
 void chem_default_gate_params(chem_gate_params *g) {
     g->tau_T = 0.5;
     g->y_min = -1e-10;
-    g->margin = 0.0;
+    g->margin = 0.01;
+    g->max_dT = 1.0;
 }
 
 int64_t chem_surrogate_param_count(void) { return surrogate_param_count(); }

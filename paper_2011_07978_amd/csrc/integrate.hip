@@ -5,11 +5,13 @@
 // (mass-action kinetics with reverse rates from equilibrium constants of the
 // NASA-7 thermo, third-body enhancement), the analytic Jacobian and the Rodas4
 // stages are evaluated cooperatively:
-//   - reaction pass, lane = reaction (stride 64): rate constants, rates of
-//     progress, and for the Jacobian the per-slot derivatives, scattered into
-//     an LDS Jacobian with LDS float atomics;
-//   - species pass, lane = species: production rates gathered through a
-//     species -> reaction CSR in fixed order;
+//   - reaction pass, lane = reaction (stride 64): rate constants and rates of
+//     progress, scattered to the production rates of their species with LDS
+//     float atomics, and for the Jacobian the per-slot derivatives, scattered
+//     into an LDS Jacobian the same way (one wavefront issues every atomic, so
+//     the order of the sums is fixed);
+//   - species pass, lane = species: dY/dt and dT/dt from the production rates,
+//     and the chain rule from concentrations to (T, Y) on the Jacobian rows;
 //   - LU with partial pivoting, row-per-lane in registers: lane r holds row r
 //     of M = I/(gamma h) - J; the pivot row is broadcast with readlane and no
 //     row is moved, each lane only remembers at which step it became pivot;

@@ -92,7 +92,7 @@ __global__ __launch_bounds__(MAP_BLOCK) void k_map_scatter(
     int64_t ncells, int N, double *__restrict__ T, double *__restrict__ Y,
     const uint8_t *__restrict__ flags, const int64_t *ref, const double *__restrict__ delta,
     const double *__restrict__ nasa_t, const double *__restrict__ invW, uint8_t *status,
-    unsigned long long *stats) {
+    uint32_t *cost, unsigned long long *stats) {
     const int64_t i = (int64_t)blockIdx.x * MAP_BLOCK + threadIdx.x;
     bool mapped = false;
     if (i < ncells && *ref >= 0 && flags[i] == 2) {
@@ -125,8 +125,11 @@ __global__ __launch_bounds__(MAP_BLOCK) void k_map_scatter(
         }
         T[i] = Tn;
         if (status) status[i] = 5;
-    } else if (i < ncells && status && flags[i] == 3) {
-        status[i] = 6;   // advanced by the surrogate before integration
+    } else if (i < ncells && flags[i] == 3) {
+        // advanced by the surrogate: its solver cost is unknown, so should the
+        // gate send it back next time it is queued first (heavy-first order)
+        if (status) status[i] = 6;
+        if (cost) cost[i] = 0x7fffffffu;
     }
     const unsigned long long cnt = __ballot(mapped);
     if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(&stats[5], (unsigned long long)__popcll(cnt));
@@ -229,11 +232,11 @@ hipError_t launch_ref_snapshot(int64_t ncells, int N, const double *T, const dou
 hipError_t launch_map_scatter(int64_t ncells, int N, double *T, double *Y, const uint8_t *flags,
                               const int64_t *ref, const double *snap, double *delta,
                               const double *nasa_t, const double *invW, uint8_t *status,
-                              unsigned long long *stats, hipStream_t s) {
+                              uint32_t *cost, unsigned long long *stats, hipStream_t s) {
     hipLaunchKernelGGL(k_ref_delta, dim3(1), dim3(64), 0, s, ncells, N, Y, ref, snap, delta);
     if (ncells > 0)
         hipLaunchKernelGGL(k_map_scatter, dim3(nblk(ncells)), dim3(MAP_BLOCK), 0, s, ncells, N, T, Y,
-                           flags, ref, delta, nasa_t, invW, status, stats);
+                           flags, ref, delta, nasa_t, invW, status, cost, stats);
     return hipGetLastError();
 }
 

@@ -283,7 +283,7 @@ struct PostParams {
     const double *nasa_t;  // species thermo [14][N] (a1..a7, a2/2, a3/3, a4/4, a5/5, ...)
     const double *invW;
     const float *norm;     // mu_x, sd_x, mu_o, sd_o, xmin, xmax
-    double tau_T, y_min, margin;
+    double tau_T, y_min, margin, max_dT;
 };
 
 __device__ __forceinline__ double pred_y(const PostParams &q, const float *outT, int m, int r, int k,
@@ -382,6 +382,7 @@ __global__ __launch_bounds__(256) void k_surrogate_post(FeatSrc f, int64_t base,
 #pragma unroll
                 for (int a = 0; a < NEL; ++a) ok = ok && isfinite(lam[a]);
                 dT = S_T * sinh((double)outT[(size_t)N * m + r] * q.norm[192 + N] + q.norm[128 + N]);
+                ok = ok && fabs(dT) <= q.max_dT;
                 // corrected state: positivity gate and the enthalpy polynomial
                 double Bo[6] = {0, 0, 0, 0, 0, 0}, Bn[6] = {0, 0, 0, 0, 0, 0};
                 for (int k = 0; k < N && ok; ++k) {
@@ -780,6 +781,7 @@ int Surrogate::apply(const FeatSrc &f, double *T, double *Y, uint8_t *flags, con
     PostParams q{};
     q.N = N; q.nel = nel; q.E = E; q.nasa_t = pin.nasa_t; q.invW = pin.invW;
     q.norm = P + weights_count(); q.tau_T = pin.tau_T; q.y_min = pin.y_min; q.margin = pin.margin;
+    q.max_dT = pin.max_dT;
     TgtSrc t{};
     for (int64_t base = 0; base < n; base += chunk) {
         const int m = (int)std::min<int64_t>(chunk, n - base);

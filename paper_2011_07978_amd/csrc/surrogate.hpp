@@ -31,7 +31,7 @@ struct TgtSrc {
 // Mechanism data the gate needs: thermo table [14][N] and 1/W [N].
 struct PostIn {
     const double *nasa_t, *invW;
-    double tau_T, y_min, margin;
+    double tau_T, y_min, margin, max_dT;
 };
 
 int64_t surrogate_param_count();

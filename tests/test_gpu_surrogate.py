@@ -163,8 +163,8 @@ def test_projection_gate_and_fallback_match_oracle():
     flags = torch.zeros(n, dtype=torch.uint8, device="cuda")
     status = torch.full((n,), 255, dtype=torch.uint8, device="cuda")
     h = torch.zeros(n, dtype=torch.float64, device="cuda")
-    s = c.integrate_surrogate(T, p, Y, f.dt, flags, gate=dict(tau_T=tau, y_min=y_min), h=h, status=status,
-                              stats=True)
+    s = c.integrate_surrogate(T, p, Y, f.dt, flags, gate=dict(tau_T=tau, y_min=y_min, max_dT=1e30),
+                              h=h, status=status, stats=True)
     torch.cuda.synchronize()
     fl, stt, Tg, Yg = host(flags), host(status), host(T), host(Y)
     acc = fl == 3
@@ -186,6 +186,18 @@ def test_projection_gate_and_fallback_match_oracle():
     rep = compare_to_oracle(dict(T=Tg[rej], Y=Yg[:, rej]), ref[0], ref[1])
     print(rep)
     assert rep["ok"], rep
+    # a largest-|dT| bound below the (common) predicted increment rejects every cell
+    nb = _norm_block(P)
+    d = synth.SUR_DIMS
+    off = sum(d[l] * d[l + 1] + d[l + 1] for l in range(4)) + d[4] * d[5]
+    dT = 1e-6 * np.sinh(float(P[off + N]) * nb["sd_o"][N] + nb["mu_o"][N])
+    i0 = int(np.nonzero(ok_o)[0][0])
+    assert not oracle.surrogate_cell(o, P, f.p[i0], f.T[i0], f.Y[:, i0], f.dt, tau_T=tau, y_min=y_min,
+                                     max_dT=0.5 * abs(dT))[0]
+    flags.zero_()
+    s = c.integrate_surrogate(dev(f.T), p, dev(f.Y), f.dt, flags,
+                              gate=dict(tau_T=tau, y_min=y_min, max_dT=0.5 * abs(dT)), stats=True)
+    assert s["cells_surrogate"] == 0 and s["cells_integrated"] == n
 
 
 def test_surrogate_leaves_mapped_and_reference_cells_alone():
@@ -207,7 +219,7 @@ def test_surrogate_leaves_mapped_and_reference_cells_alone():
         f0 = host(flags).copy()
         st = torch.zeros(n, dtype=torch.uint8, device="cuda")
         if use_sur:
-            s = c.integrate_surrogate(T, p, Y, f.dt, flags, ref, gate=dict(tau_T=1e9, y_min=-1.0), status=st,
+            s = c.integrate_surrogate(T, p, Y, f.dt, flags, ref, gate=dict(tau_T=1e9, y_min=-1.0, max_dT=1e30), status=st,
                                       stats=True)
         else:
             s = c.integrate(T, p, Y, f.dt, flags=flags, ref_index=ref, status=st, stats=True)

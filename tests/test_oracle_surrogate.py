@@ -143,6 +143,10 @@ def test_surrogate_cell_gate_and_conservation():
     E = (mech.composition.T / mech.W[None, :])
     assert np.abs(E @ (Y1 - Y)).max() <= 1e-15
     assert abs(o.enthalpy(T1, Y1) - o.enthalpy(T, Y)) <= 1e-12 * o.cp(T, Y) * T
+    # a predicted |dT| above max_dT is rejected, the state untouched
+    ok3, T3, Y3 = oracle.surrogate_cell(o, P, f.p[i], T, Y, 1e-6, tau_T=1e9, y_min=-1.0, max_dT=0.0)
+    dT_pred = abs(T1 - T)
+    assert (not ok3 and T3 == T and np.array_equal(Y3, Y)) or dT_pred == 0.0
     # out-of-box input is rejected
     P2 = P.copy()
     base = P2.size - 6 * IN
