@@ -146,7 +146,7 @@ def train_surrogate(chem, mech, args, torch, accounting):
     log(f"surrogate: {pairs.n} pairs in {t_pairs:.1f} s, {args.sur_epochs} epochs in {t_train:.1f} s, "
         f"loss {hist[0]:.3e} -> {hist[-1]:.3e}")
     val = surrogate.validate(chem, va, gate=dict(tau_T=args.tau_T, margin=args.margin,
-                                                 max_dT=args.max_dT))
+                                                 max_dT=args.max_dT, T_max=args.T_max))
     fl = accounting.surrogate_train_flops_per_sample(mech.n_species) * tr.n * args.sur_epochs
     return dict(pairs=pairs.n, train_pairs=tr.n, validation_pairs=va.n, epochs=args.sur_epochs,
                 seconds_pairs=t_pairs, seconds_train=t_train,
@@ -302,6 +302,7 @@ def main():
     ap.add_argument("--tau-T", type=float, default=0.5)
     ap.add_argument("--margin", type=float, default=0.01, help="gate: training-box margin")
     ap.add_argument("--max-dT", type=float, default=1.0, help="gate: largest predicted |dT| (K)")
+    ap.add_argument("--T-max", type=float, default=1000.0, help="gate: hottest cell offered (K)")
     ap.add_argument("--graph", action="store_true",
                     help="also time the balanced steps recorded into one HIP graph")
     ap.add_argument("--autotune", action="store_true",
@@ -330,7 +331,8 @@ def main():
     threads = min(16, os.cpu_count() or 1)
 
     sur = None
-    gate = dict(tau_T=args.tau_T, y_min=-1e-10, margin=args.margin, max_dT=args.max_dT)
+    gate = dict(tau_T=args.tau_T, y_min=-1e-10, margin=args.margin, max_dT=args.max_dT,
+                T_max=args.T_max)
     if use_sur:
         sur = train_surrogate(chem, mech, args, torch, accounting)
     chem.reserve(field.n_cells)
@@ -380,8 +382,15 @@ def main():
     kms = [s["ms_integrate"] for s in st_h]
     achieved = float(np.mean([f / (m * 1e-3) / 1e12 for f, m in zip(fl, kms)]))
     kname = "k_big_queue" if mech.n_species + 1 > 64 else "k_integrate_queue"
+    # HBM bytes per integrated cell and launch of the wavefront kernel, from
+    # rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 1 GiB copy
+    # (profiles/k_integrate_queue_54__pmc_traffic_mapped_262k.md)
+    traffic = None
+    if kname == "k_integrate_queue" and mech.n_species == 53:
+        traffic = 8633.0 * float(np.mean([s["cells_integrated"] for s in st_h]))
     roof = dict(bound="alu", achieved=achieved, peak=accounting.FP64_VECTOR_PEAK_TFLOPS,
-                unit="TFLOP/s", frac=achieved / accounting.FP64_VECTOR_PEAK_TFLOPS, traffic=None,
+                unit="TFLOP/s", frac=achieved / accounting.FP64_VECTOR_PEAK_TFLOPS, traffic=traffic,
+                traffic_unit="bytes per launch" if traffic else None,
                 kernel=kname, kernel_ms=float(np.mean(kms)),
                 flops_per_launch=float(np.mean(fl)),
                 steps_per_launch=float(np.mean([s["steps_accepted"] + s["steps_rejected"]
@@ -412,8 +421,8 @@ def main():
 
     desc = (f"{args.workload}: {field.n_cells} cells, {mech.n_species} species / "
             f"{mech.n_reactions} reactions, dt {field.dt} s, rtol 1e-8, atol 1e-12, map (Z_tol 1e-4)"
-            + (" + BF16 MLP surrogate with conservation and gate (tau_T %g K, max |dT| %g K)"
-               % (args.tau_T, args.max_dT)
+            + (" + BF16 MLP surrogate with conservation and gate (tau_T %g K, max |dT| %g K, T <= %g K)"
+               % (args.tau_T, args.max_dT, args.T_max)
                if use_sur else "")
             + " + heavy-first queue + Rodas4 + mapped update")
     out = {

@@ -157,10 +157,10 @@ typedef struct {
  * 1/Y1: Y' = Y1 - Y1 (E^T lam), (E diag(Y1) E^T) lam = E (Y1 - Y),
  * E_ek = a_ek / W_k (species at zero stay there; corrections are proportional
  * to each species' mass fraction).  T' solves h(T', Y') = h(T, Y).  The gate
- * (chem_gate_params) sends a cell back to the Rosenbrock solver unless every
- * raw feature lies in [xmin - margin*(xmax - xmin), xmax + margin*(xmax -
- * xmin)], |dT| <= max_dT, E diag(Y1) E^T is invertible, every Y'_k >= y_min
- * and |T + dT - T'| <= tau_T.
+ * (chem_gate_params) sends a cell back to the Rosenbrock solver unless
+ * T <= T_max, every raw feature lies in [xmin - margin*(xmax - xmin), xmax +
+ * margin*(xmax - xmin)], |dT| <= max_dT, E diag(Y1) E^T is invertible, every
+ * Y'_k >= y_min and |T + dT - T'| <= tau_T.
  * Available for N <= 61 species and E <= 8 elements with E E^T invertible
  * (otherwise the surrogate entry points return CHEM_E_UNIMPL). */
 typedef struct {
@@ -183,6 +183,10 @@ typedef struct {
                              solver (default 1: the surrogate takes slowly
                              changing cells; igniting cells stay on the FP64
                              path) */
+    double T_max;         /* K: cells hotter than this go to the solver (default
+                             1000: above it chemistry is fast, and a relative
+                             error of the network on the large increments
+                             exceeds the 1 K accuracy target) */
 } chem_gate_params;
 
 /* Create a context on HIP device `hip_device`, enqueueing on `hip_stream`

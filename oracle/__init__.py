@@ -288,13 +288,15 @@ def conserve(o, Y0, Y1):
     return None if rc else y
 
 
-def surrogate_cell(o, params, p, T, Y, dt, tau_T=0.5, y_min=-1e-10, margin=0.0, max_dT=np.inf):
+def surrogate_cell(o, params, p, T, Y, dt, tau_T=0.5, y_min=-1e-10, margin=0.0, max_dT=np.inf,
+                   T_max=np.inf):
     P = np.ascontiguousarray(params, np.float32)
     Tc = C.c_double(T)
     Yc = _f64(Y).copy()
     ok = lib().orc_surrogate_cell(o.h, P.ctypes.data_as(C.POINTER(C.c_float)), C.c_double(p),
                                   C.byref(Tc), _p(Yc), C.c_double(dt), C.c_double(tau_T),
-                                  C.c_double(y_min), C.c_double(margin), C.c_double(max_dT))
+                                  C.c_double(y_min), C.c_double(margin), C.c_double(max_dT),
+                                  C.c_double(T_max))
     return bool(ok), Tc.value, Yc
 
 

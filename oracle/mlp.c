@@ -233,17 +233,18 @@ int orc_conserve(const omech *m, const double *Y0, double *Y1)
 
 /* One surrogate step for one cell (raw state in/out); returns 1 if the gate
  * accepts (state updated), 0 if the cell must go to the Rosenbrock solver.
- * Gate: every raw feature inside the training box widened by margin times its
- * span, |dT| <= max_dT, E diag(Y1) E^T invertible, Y' >= y_min,
- * |T + dT - T'| <= tau_T. */
+ * Gate: T <= T_max, every raw feature inside the training box widened by
+ * margin times its span, |dT| <= max_dT, E diag(Y1) E^T invertible,
+ * Y' >= y_min, |T + dT - T'| <= tau_T. */
 int orc_surrogate_cell(const omech *m, const float *P, double p, double *T, double *Y, double dt,
-                       double tau_T, double y_min, double margin, double max_dT)
+                       double tau_T, double y_min, double margin, double max_dT, double T_max)
 {
     const int N = m->N;
     const float *nb = norm_block(P);
     const float *mu_o = nb + 2 * IN_PAD, *sd_o = nb + 3 * IN_PAD;
     const float *xmin = nb + 4 * IN_PAD, *xmax = nb + 5 * IN_PAD;
     double x[IN_PAD], out[OUT_PAD];
+    if (!(*T <= T_max)) return 0;
     orc_mlp_features(N, *T, p, Y, dt, x);
     for (int i = 0; i < N + 3; ++i) {
         double span = (double)xmax[i] - (double)xmin[i];

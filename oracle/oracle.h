@@ -144,7 +144,7 @@ double orc_mlp_loss_grad(const float *P, int64_t n, int nfeat, int nout, const d
                          const double *target, int bf16, double *grad);
 int orc_conserve(const omech *m, const double *Y0, double *Y1);
 int orc_surrogate_cell(const omech *m, const float *P, double p, double *T, double *Y, double dt,
-                       double tau_T, double y_min, double margin, double max_dT);
+                       double tau_T, double y_min, double margin, double max_dT, double T_max);
 
 #ifdef __cplusplus
 }

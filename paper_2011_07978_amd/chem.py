@@ -62,7 +62,7 @@ class TrainParams(C.Structure):
 
 class GateParams(C.Structure):
     _fields_ = [("tau_T", C.c_double), ("y_min", C.c_double), ("margin", C.c_double),
-                ("max_dT", C.c_double)]
+                ("max_dT", C.c_double), ("T_max", C.c_double)]
 
 
 class TuneEntry(C.Structure):

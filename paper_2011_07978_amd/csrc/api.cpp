@@ -19,6 +19,7 @@ int pick_np(int n);
 hipError_t launch_integrate(int NP, const MechDev &M, const MechDev *Md, const IntParams &P,
                             int schedule, int grid, hipStream_t s);
 int queue_occupancy(int NP, const MechDev &M);
+int wave_kernel_wpb(const MechDev &M);
 hipError_t launch_eval_rhs_jac(int NP, const MechDev &M, const MechDev *Md, const IntParams &P,
                                double *f, double *J, hipStream_t s);
 hipError_t launch_rodas_step(int NP, const MechDev &M, const MechDev *Md, const IntParams &P,
@@ -466,7 +467,7 @@ int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
     }
     c->NP = pick_np(M.n);
     c->occ = 0;
-    if (c->NP > 0 && (size_t)M.lds_doubles * 8 <= 160 * 1024) c->occ = queue_occupancy(c->NP, M);
+    if (c->NP > 0 && wave_kernel_wpb(M) > 0) c->occ = queue_occupancy(c->NP, M);
     if (c->NP < 0) {
         // workgroup-per-cell path: the iteration matrix must fit in one CU's LDS
         int max_lds = 0;
@@ -581,8 +582,8 @@ static int check_integrator(chem_ctx *c) {
     if (c->NP < 0)
         return fail(c, CHEM_E_UNIMPL, "%d species: the iteration matrix does not fit in one CU's "
                                       "LDS", c->N);
-    if ((size_t)c->M.lds_doubles * 8 > 160 * 1024)
-        return fail(c, CHEM_E_UNIMPL, "mechanism tables exceed LDS (%d bytes)", c->M.lds_doubles * 8);
+    if (wave_kernel_wpb(c->M) == 0)
+        return fail(c, CHEM_E_UNIMPL, "mechanism tables and one cell's Jacobian exceed LDS");
     return CHEM_OK;
 }
 
@@ -616,7 +617,8 @@ static int integrate_core(chem_ctx *c, int64_t n, double *T, const double *p, do
         if (gate) {
             if (stats) HIPCHK(c, hipEventRecord(c->ev4, s));
             FeatSrc f{T, p, Y, nullptr, dt, n, c->N};
-            PostIn pin{c->M.nasa_t, c->M.invW, gate->tau_T, gate->y_min, gate->margin, gate->max_dT};
+            PostIn pin{c->M.nasa_t, c->M.invW, gate->tau_T, gate->y_min, gate->margin, gate->max_dT,
+                       gate->T_max};
             char err[256] = {0};
             if (c->sur->apply(f, T, Y, flags, pin, c->d_stats, s, err))
                 return fail(c, CHEM_E_HIP, "surrogate: %s", err);
@@ -706,7 +708,7 @@ int chem_integrate_surrogate(chem_ctx *c, int64_t n, double *T, const double *p,
         return fail(c, CHEM_E_INVALID_ARG, "chem_integrate_surrogate: bad n, dt or gate");
     if (n > 0 && (!T || !p || !Y || !flags)) return fail(c, CHEM_E_INVALID_ARG, "null state or flags array");
     if (!(gate->tau_T >= 0.0) || !(gate->margin >= 0.0) || gate->y_min != gate->y_min ||
-        !(gate->max_dT >= 0.0))
+        !(gate->max_dT >= 0.0) || gate->T_max != gate->T_max)
         return fail(c, CHEM_E_INVALID_ARG, "bad gate parameters");
     return integrate_core(c, n, T, p, Y, dt, flags, ref_index, h, cost, status, steps, stats, gate);
 }
@@ -726,6 +728,7 @@ void chem_default_gate_params(chem_gate_params *g) {
     g->y_min = -1e-10;
     g->margin = 0.01;
     g->max_dT = 1.0;
+    g->T_max = 1000.0;
 }
 
 int64_t chem_surrogate_param_count(void) { return surrogate_param_count(); }

@@ -49,11 +49,28 @@ __device__ __forceinline__ void lds_add(double *p, double v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// A workgroup holds up to four wavefronts, each integrating its own cells in
+// its own LDS region; they share one LDS copy of the species and reaction
+// records (placed first).  Within a cell only the wavefront synchronises: LDS
+// operations of one wavefront complete in order, so ordering them needs a
+// compiler barrier and a wavefront-scope fence, not a workgroup barrier.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+extern __shared__ double lds_all[];
+
+__host__ __device__ inline int table_doubles(const MechDev &M) {
+    return M.N * SPC_STRIDE + M.R * (int)(sizeof(RxnRec) / sizeof(double));
+}
+
 // -----------------------------------------------------------------------------
 // f(y), and with JAC the analytic Jacobian into LDS (row-major, stride ldj).
 // Returns f_r on lane r.  All lanes of the wave must call it.
 // -----------------------------------------------------------------------------
-template <bool JAC>
+template <bool JAC, bool LT>
 __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const double p,
                                            const double y, double *__restrict__ lds) {
     // The memory clobber keeps the descriptor loads, and the opaque lane index
@@ -82,7 +99,7 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
     // species thermo (NASA-7 single range), Horner form
     double cpR = 0.0, hRT = 0.0, gRT = 0.0, dcpR = 0.0, invWk = 0.0, Wk = 0.0;
     if (sp) {
-        const auto *a = gbl(M.spc) + k * SPC_STRIDE;
+        const double *a = LT ? lds_all + k * SPC_STRIDE : (const double *)(gbl(M.spc) + k * SPC_STRIDE);
         const double a1 = a[0], a2 = a[1], a3 = a[2], a4 = a[3], a5 = a[4], a6 = a[5], a7 = a[6];
         const double h2 = a[7], h3 = a[8], h4 = a[9], h5 = a[10];
         const double s3 = a[11], s4 = a[12], s5 = a[13];
@@ -112,13 +129,14 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
         for (int i = lane; i < n * ldj; i += 64) Jl[i] = 0.0;
         if (lane < n) tbl[lane] = 0.0;
     }
-    __syncthreads();
+    wave_sync();
 
     // reaction pass: rates of progress scattered to the production rates of
     // their reactant and product slots (LDS float atomics; missing slots hit
     // the sentinel entry N)
     const double ln_patm_RT = log(P_ATM / (RU_ERG * T));
-    const auto *rxn = gbl(M.rxn);
+    const RxnRec *rxn = LT ? reinterpret_cast<const RxnRec *>(lds_all + N * SPC_STRIDE)
+                           : (const RxnRec *)gbl(M.rxn);
     auto reaction = [&](const int j, const bool valid) {
         const auto &rec = rxn[j];
         const int ix0 = rec.idx[0], ix1 = rec.idx[1], ix2 = rec.idx[2], ix3 = rec.idx[3];
@@ -193,7 +211,7 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
         reaction(j, true);
         reaction(v2 ? j + 64 : j, v2);
     }
-    __syncthreads();
+    wave_sync();
 
     // species: dY_k/dt = W_k omega_k / rho; dT/dt = -sum_k H_k omega_k / (rho cp)
     const double fk = sp ? Wk * wl[k] / rho : 0.0;
@@ -219,12 +237,19 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
             if (l < N) s0 += (row[1 + l] + tbk) * Cl[l];
             const double s = s0 + s1;
             const double cst = fk * Wbar - Wk * Wbar * s / rho;
-            const auto *iw = gbl(M.invW);
+            if (LT) {
+                // 1/W_i from the species records in the shared table (broadcast reads)
 #pragma unroll 8
-            for (int i = 0; i < N; ++i) row[1 + i] = iw[i] * (Wk * (row[1 + i] + tbk) + cst);
+                for (int i = 0; i < N; ++i)
+                    row[1 + i] = lds_all[i * SPC_STRIDE + 15] * (Wk * (row[1 + i] + tbk) + cst);
+            } else {
+                const auto *iw = gbl(M.invW);
+#pragma unroll 8
+                for (int i = 0; i < N; ++i) row[1 + i] = iw[i] * (Wk * (row[1 + i] + tbk) + cst);
+            }
             row[0] = Wk / rho * (row[0] - s * invT) + fk * invT;
         }
-        __syncthreads();
+        wave_sync();
         // temperature row: J_T,c = -(sum_k e_k J_kc)/cp - f_T dcp/dy_c / cp
         if (lane < n) {
             double a0 = 0.0, a1 = 0.0;
@@ -241,7 +266,7 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
             else v = -acc / cps - fT * cpl[lane - 1] / cps;
             Jl[lane] = v;
         }
-        __syncthreads();
+        wave_sync();
     }
     return lane == 0 ? fT : fk;
 }
@@ -338,7 +363,7 @@ __device__ __forceinline__ void build_matrix(const MechDev *__restrict__ Mp,
 
 // One Rodas4 attempt of size h from y (f0 = f(y), J in LDS).  Returns false
 // when M is singular.  ynew and err are per lane.
-template <int NP>
+template <int NP, bool LT>
 __device__ __forceinline__ bool rodas_attempt(const MechDev *__restrict__ M, double p, double y,
                                               double f0, double h, double *lds, double &ynew,
                                               double &err) {
@@ -359,7 +384,7 @@ __device__ __forceinline__ bool rodas_attempt(const MechDev *__restrict__ M, dou
             ys += kRodasA[s][2] * u2;
             ys += kRodasA[s][3] * u3;
             ys += kRodasA[s][4] * u4;
-            rv = rhs_eval<false>(M, p, ys, lds);
+            rv = rhs_eval<false, LT>(M, p, ys, lds);
             rv += (kRodasC[s][0] / h) * u0;
             rv += (kRodasC[s][1] / h) * u1;
             rv += (kRodasC[s][2] / h) * u2;
@@ -379,20 +404,43 @@ __device__ __forceinline__ bool rodas_attempt(const MechDev *__restrict__ M, dou
     return true;
 }
 
-__device__ __forceinline__ void init_sentinels(const MechDev *Mp, double *lds) {
+// With LT, copies the species and reaction records into the shared LDS table
+// (whole workgroup, once per launch); returns this wavefront's region with its
+// sentinel entries set.
+template <bool LT>
+__device__ __forceinline__ double *init_lds(const MechDev *Mp) {
     const MechDev &M = *Mp;
-    if (threadIdx.x == 0) {
+    if (!LT) {
+        // one wavefront per workgroup, records read from global memory
+        double *lds = lds_all;
+        if (lane_id() == 0) {
+            lds[M.off_C + M.N] = 1.0;
+            lds[M.off_g + M.N] = 0.0;
+            lds[M.off_h + M.N] = 0.0;
+        }
+        wave_sync();
+        return lds;
+    }
+    const int ns = M.N * SPC_STRIDE, nr = M.R * (int)(sizeof(RxnRec) / sizeof(double));
+    const auto *spc = gbl(M.spc);
+    const double *rxd = reinterpret_cast<const double *>(M.rxn);
+    for (int i = threadIdx.x; i < ns; i += blockDim.x) lds_all[i] = spc[i];
+    for (int i = threadIdx.x; i < nr; i += blockDim.x) lds_all[ns + i] = gbl(rxd)[i];
+    __syncthreads();
+    double *lds = lds_all + ns + nr + (threadIdx.x >> 6) * M.lds_doubles;
+    if (lane_id() == 0) {
         lds[M.off_C + M.N] = 1.0;
         lds[M.off_g + M.N] = 0.0;
         lds[M.off_h + M.N] = 0.0;
     }
-    __syncthreads();
+    wave_sync();
+    return lds;
 }
 
 // -----------------------------------------------------------------------------
 // Adaptive integration of one cell over [0, dt]
 // -----------------------------------------------------------------------------
-template <int NP>
+template <int NP, bool LT>
 __device__ __forceinline__ void integrate_cell(const MechDev *__restrict__ M, const IntParams &P,
                                                int64_t cell, double *lds) {
     const int lane = lane_id();
@@ -421,14 +469,14 @@ __device__ __forceinline__ void integrate_cell(const MechDev *__restrict__ M, co
     double hnext = h, t = 0.0;
     int nacc = 0, nrej = 0, status = 0;
     bool rej_last = false;
-    double f0 = rhs_eval<true>(M, p, y, lds);
+    double f0 = rhs_eval<true, LT>(M, p, y, lds);
     while (t < dt) {
         if (nacc + nrej >= P.max_steps) { status = 1; break; }
         bool last = false;
         if (h >= dt - t) { h = dt - t; last = true; }
         if (h < P.hmin_frac * dt) { status = 2; break; }
         double ynew = 0.0, ev = 0.0;
-        const bool ok = rodas_attempt<NP>(M, p, y, f0, h, lds, ynew, ev);
+        const bool ok = rodas_attempt<NP, LT>(M, p, y, f0, h, lds, ynew, ev);
         double e = 0.0;
         bool bad = !ok;
         if (ok) {
@@ -446,7 +494,7 @@ __device__ __forceinline__ void integrate_cell(const MechDev *__restrict__ M, co
             hnext = uniform_d(h * fac);
             h = hnext;
             rej_last = false;
-            if (t < dt) f0 = rhs_eval<true>(M, p, y, lds);
+            if (t < dt) f0 = rhs_eval<true, LT>(M, p, y, lds);
         } else {
             const double fac = bad ? 0.2 : fmax(0.2, 0.9 * pow(e, -0.25));
             h = uniform_d(h * fac);
@@ -470,26 +518,27 @@ __device__ __forceinline__ void integrate_cell(const MechDev *__restrict__ M, co
     }
 }
 
+// Static launch: workgroup i (one wavefront) integrates cell i, reading the
+// records from global memory (an LDS copy per cell would cost more than it
+// saves).
 template <int NP>
 __global__ __launch_bounds__(64) void k_integrate_plain(const MechDev *__restrict__ M, IntParams P) {
-    extern __shared__ double lds[];
-    init_sentinels(M, lds);
+    double *lds = init_lds<false>(M);
     const int64_t cell = blockIdx.x;
     if (P.flags && P.flags[cell] >= 2) return;
-    integrate_cell<NP>(M, P, cell, lds);
+    integrate_cell<NP, false>(M, P, cell, lds);
 }
 
-// Persistent workgroups draw cells from NSEG segments of the heavy-first queue
-// (segment x holds sorted positions x, x + NSEG, ...); a workgroup starts on
-// segment blockIdx % NSEG and steals from the next segments once its own is
-// drained.  Every workgroup exits after NSEG consecutive empty segments.
+// Persistent wavefronts draw cells from NSEG segments of the heavy-first queue
+// (segment x holds sorted positions x, x + NSEG, ...); wavefront w starts on
+// segment w % NSEG and steals from the next segments once its own is drained.
+// Every wavefront exits after NSEG consecutive empty segments.
 template <int NP>
-__global__ __launch_bounds__(64) void k_integrate_queue(const MechDev *__restrict__ M, IntParams P) {
-    extern __shared__ double lds[];
-    init_sentinels(M, lds);
+__global__ __launch_bounds__(256) void k_integrate_queue(const MechDev *__restrict__ M, IntParams P) {
+    double *lds = init_lds<true>(M);
     const int nact = uniform_i(*P.n_active);
     const int chunk = P.chunk;
-    int seg = blockIdx.x % NSEG;
+    int seg = (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % NSEG);
     int probes = 0;
     while (probes < NSEG) {
         int c = 0;
@@ -506,7 +555,7 @@ __global__ __launch_bounds__(64) void k_integrate_queue(const MechDev *__restric
             const int pos = first + NSEG * q;
             if (pos >= nact) break;
             const int64_t cell = P.queue[pos];
-            integrate_cell<NP>(M, P, cell, lds);
+            integrate_cell<NP, true>(M, P, cell, lds);
         }
     }
 }
@@ -515,14 +564,13 @@ __global__ __launch_bounds__(64) void k_integrate_queue(const MechDev *__restric
 template <int NP>
 __global__ __launch_bounds__(64) void k_eval_rhs_jac(const MechDev *__restrict__ M, IntParams P,
                                                      double *fout, double *Jout) {
-    extern __shared__ double lds[];
-    init_sentinels(M, lds);
+    double *lds = init_lds<true>(M);
     const int64_t cell = blockIdx.x;
     const int lane = lane_id(), n = M->n, N = M->N;
     double y = 0.0;
     if (lane == 0) y = P.T[cell];
     else if (lane <= N) y = P.Y[(int64_t)(lane - 1) * P.ncells + cell];
-    const double f = rhs_eval<true>(M, P.p[cell], y, lds);
+    const double f = rhs_eval<true, true>(M, P.p[cell], y, lds);
     if (fout && lane < n) fout[cell * n + lane] = f;
     if (Jout)
         for (int i = lane; i < n * n; i += 64)
@@ -532,17 +580,16 @@ __global__ __launch_bounds__(64) void k_eval_rhs_jac(const MechDev *__restrict__
 template <int NP>
 __global__ __launch_bounds__(64) void k_rodas_step(const MechDev *__restrict__ M, IntParams P,
                                                    double h, double *ynew_out, double *err_out) {
-    extern __shared__ double lds[];
-    init_sentinels(M, lds);
+    double *lds = init_lds<true>(M);
     const int64_t cell = blockIdx.x;
     const int lane = lane_id(), n = M->n, N = M->N;
     double y = 0.0;
     if (lane == 0) y = P.T[cell];
     else if (lane <= N) y = P.Y[(int64_t)(lane - 1) * P.ncells + cell];
     const double p = P.p[cell];
-    const double f0 = rhs_eval<true>(M, p, y, lds);
+    const double f0 = rhs_eval<true, true>(M, p, y, lds);
     double ynew = 0.0, err = 0.0;
-    const bool ok = rodas_attempt<NP>(M, p, y, f0, h, lds, ynew, err);
+    const bool ok = rodas_attempt<NP, true>(M, p, y, f0, h, lds, ynew, err);
     if (!ok) { ynew = NAN; err = NAN; }
     if (lane < n) {
         ynew_out[cell * n + lane] = ynew;
@@ -562,22 +609,34 @@ int pick_np(int n) {
     return -1;
 }
 
-static size_t lds_bytes(const MechDev &M) { return sizeof(double) * (size_t)M.lds_doubles; }
+// Wavefronts per workgroup: as many as fit in one CU's LDS next to the shared
+// record table (4 for the 53-species mechanism: 28 KB of records + 4 x 28 KB).
+static constexpr size_t kLdsCap = 160 * 1024;
+int wave_kernel_wpb(const MechDev &M) {
+    for (int w : {4, 2, 1})
+        if (sizeof(double) * ((size_t)table_doubles(M) + (size_t)w * M.lds_doubles) <= kLdsCap) return w;
+    return 0;
+}
+static size_t lds_bytes(const MechDev &M, int wpb) {
+    return sizeof(double) * ((size_t)table_doubles(M) + (size_t)wpb * M.lds_doubles);
+}
 
 // Host launchers: M is the host copy (sizes), Md the device copy the kernels read.
 
 template <int NP>
 static hipError_t launch_integrate_np(const MechDev &M, const MechDev *Md, const IntParams &P,
                                       int schedule, int grid, hipStream_t s) {
-    const size_t sh = lds_bytes(M);
+    const int wpb = wave_kernel_wpb(M);
+    const size_t sh = lds_bytes(M, wpb);
     if (schedule == 0) {
+        const size_t sh1 = sizeof(double) * (size_t)M.lds_doubles;
         hipFuncSetAttribute((const void *)k_integrate_plain<NP>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-        hipLaunchKernelGGL(k_integrate_plain<NP>, dim3((unsigned)P.ncells), dim3(64), sh, s, Md, P);
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh1);
+        hipLaunchKernelGGL(k_integrate_plain<NP>, dim3((unsigned)P.ncells), dim3(64), sh1, s, Md, P);
     } else {
         hipFuncSetAttribute((const void *)k_integrate_queue<NP>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-        hipLaunchKernelGGL(k_integrate_queue<NP>, dim3((unsigned)grid), dim3(64), sh, s, Md, P);
+        hipLaunchKernelGGL(k_integrate_queue<NP>, dim3((unsigned)grid), dim3(64 * wpb), sh, s, Md, P);
     }
     return hipGetLastError();
 }
@@ -592,15 +651,18 @@ hipError_t launch_integrate(int NP, const MechDev &M, const MechDev *Md, const I
     return hipErrorInvalidValue;
 }
 
+// Workgroups of the queue kernel that fit on one CU.
 int queue_occupancy(int NP, const MechDev &M) {
     int blocks = 0;
-    const size_t sh = lds_bytes(M);
+    const int wpb = wave_kernel_wpb(M);
+    if (wpb == 0) return 0;
+    const size_t sh = lds_bytes(M, wpb);
     switch (NP) {
 #define CASE(v)                                                                                 \
     case v:                                                                                     \
         hipFuncSetAttribute((const void *)k_integrate_queue<v>,                                 \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);               \
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_integrate_queue<v>, 64, sh);    \
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_integrate_queue<v>, 64 * wpb, sh); \
         break;
         CHEM_NP_LIST(CASE)
 #undef CASE
@@ -610,7 +672,7 @@ int queue_occupancy(int NP, const MechDev &M) {
 
 hipError_t launch_eval_rhs_jac(int NP, const MechDev &M, const MechDev *Md, const IntParams &P,
                                double *f, double *J, hipStream_t s) {
-    const size_t sh = lds_bytes(M);
+    const size_t sh = lds_bytes(M, 1);
     switch (NP) {
 #define CASE(v)                                                                                 \
     case v:                                                                                     \
@@ -626,7 +688,7 @@ hipError_t launch_eval_rhs_jac(int NP, const MechDev &M, const MechDev *Md, cons
 
 hipError_t launch_rodas_step(int NP, const MechDev &M, const MechDev *Md, const IntParams &P,
                              double h, double *ynew, double *err, hipStream_t s) {
-    const size_t sh = lds_bytes(M);
+    const size_t sh = lds_bytes(M, 1);
     switch (NP) {
 #define CASE(v)                                                                                 \
     case v:                                                                                     \

@@ -243,12 +243,28 @@ __global__ __launch_bounds__(256) void k_gelu_back(const float *dH, const float 
     dZT[(size_t)c * ldt + r] = gb;
 }
 
-// column sums of src [B x ncol] (bias gradients), one thread per column
-__global__ __launch_bounds__(256) void k_colsum(const float *src, int B, int ncol, float *dst) {
+// Column sums of src [B x ncol] (bias gradients) in two fixed-order passes:
+// block (x, y) sums rows y, y + CS_CHUNKS, ... of 64 columns into part[y][c]
+// (four row phases per block, combined in order); then one thread per column
+// adds the CS_CHUNKS partial sums in order.
+constexpr int CS_CHUNKS = 64;
+__global__ __launch_bounds__(256) void k_colsum_part(const float *src, int B, int ncol, float *part) {
+    const int c = blockIdx.x * 64 + (threadIdx.x & 63), ph = threadIdx.x >> 6;
+    float s = 0.0f;
+    if (c < ncol)
+        for (int r = blockIdx.y + CS_CHUNKS * ph; r < B; r += 4 * CS_CHUNKS) s += src[(size_t)r * ncol + c];
+    __shared__ float sh[4][64];
+    sh[ph][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (ph == 0 && c < ncol)
+        part[(size_t)blockIdx.y * ncol + c] = (sh[0][threadIdx.x] + sh[1][threadIdx.x]) +
+                                              (sh[2][threadIdx.x] + sh[3][threadIdx.x]);
+}
+__global__ __launch_bounds__(256) void k_colsum_final(const float *part, int ncol, float *dst) {
     const int c = blockIdx.x * 256 + threadIdx.x;
     if (c >= ncol) return;
     float s = 0.0f;
-    for (int r = 0; r < B; ++r) s += src[(size_t)r * ncol + c];
+    for (int y = 0; y < CS_CHUNKS; ++y) s += part[(size_t)y * ncol + c];
     dst[c] = s;
 }
 
@@ -283,7 +299,7 @@ struct PostParams {
     const double *nasa_t;  // species thermo [14][N] (a1..a7, a2/2, a3/3, a4/4, a5/5, ...)
     const double *invW;
     const float *norm;     // mu_x, sd_x, mu_o, sd_o, xmin, xmax
-    double tau_T, y_min, margin, max_dT;
+    double tau_T, y_min, margin, max_dT, T_max;
 };
 
 __device__ __forceinline__ double pred_y(const PostParams &q, const float *outT, int m, int r, int k,
@@ -310,7 +326,7 @@ __global__ __launch_bounds__(256) void k_surrogate_post(FeatSrc f, int64_t base,
         const int N = q.N;
         if (!flags || flags[i] == 0) {
             tried = true;
-            bool ok = true;
+            bool ok = T[i] <= q.T_max;
             // out-of-distribution box on the raw features
             for (int c = 0; c < N + 3 && ok; ++c) {
                 const double v = raw_feature(f, i, c);
@@ -557,6 +573,7 @@ int Surrogate::reserve_ws(int B, bool training, char *err) {
         SCHK(get32(&dZf, (size_t)B * S_HID));
         SCHK(get16(&dZb, (size_t)B * S_HID));
         SCHK(get16(&dZbT, (size_t)B * S_HID));
+        SCHK(get32(&csum, (size_t)CS_CHUNKS * S_HID));
     }
     int *ip = nullptr;
     SCHK(dalloc(&ip, (size_t)B)); ws.push_back(ip); idx = ip;
@@ -590,6 +607,12 @@ void Surrogate::forward(int B, bool training, bool out_transposed, hipStream_t s
     }
 }
 
+void Surrogate::colsum(const float *src, int B, int ncol, float *dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_colsum_part, dim3((ncol + 63) / 64, CS_CHUNKS), dim3(256), 0, s, src, B, ncol,
+                       csum);
+    hipLaunchKernelGGL(k_colsum_final, dim3((ncol + 255) / 256), dim3(256), 0, s, csum, ncol, dst);
+}
+
 // gradients of the mean-squared error for the B rows in X / Tg into G
 void Surrogate::backward(int B, hipStream_t s) {
     const int nout = N + 1;
@@ -600,8 +623,7 @@ void Surrogate::backward(int B, hipStream_t s) {
         GemmEpi e{};
         e.C = G + layer_offset(4); e.ldc = S_HID;
         gemm<EPI_PLAIN>(dZ5T, B, HT[3], B, S_OUT, S_HID, B, e, s);          // dW5 = dZ5^T H4
-        hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, s, dOf, B, S_OUT,
-                           G + layer_offset(4) + (int64_t)S_OUT * S_HID);
+        colsum(dOf, B, S_OUT, G + layer_offset(4) + (int64_t)S_OUT * S_HID, s);
         GemmEpi e2{};
         e2.C = dH; e2.ldc = S_HID;
         gemm<EPI_PLAIN>(dZ5, S_OUT, WbT[4], S_OUT, B, S_HID, S_OUT, e2, s);    // dH4 = dZ5 W5
@@ -614,8 +636,7 @@ void Surrogate::backward(int B, hipStream_t s) {
         e.C = G + layer_offset(l); e.ldc = ni;
         const uint16_t *inT = l == 0 ? XT : HT[l - 1];
         gemm<EPI_PLAIN>(dZbT, B, inT, B, S_HID, ni, B, e, s);               // dW = dZ^T h_{l-1}
-        hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, s, dZf, B, S_HID,
-                           G + layer_offset(l) + (int64_t)S_HID * ni);
+        colsum(dZf, B, S_HID, G + layer_offset(l) + (int64_t)S_HID * ni, s);
         if (l > 0) {
             GemmEpi e2{};
             e2.C = dH; e2.ldc = S_HID;
@@ -782,6 +803,7 @@ int Surrogate::apply(const FeatSrc &f, double *T, double *Y, uint8_t *flags, con
     q.N = N; q.nel = nel; q.E = E; q.nasa_t = pin.nasa_t; q.invW = pin.invW;
     q.norm = P + weights_count(); q.tau_T = pin.tau_T; q.y_min = pin.y_min; q.margin = pin.margin;
     q.max_dT = pin.max_dT;
+    q.T_max = pin.T_max;
     TgtSrc t{};
     for (int64_t base = 0; base < n; base += chunk) {
         const int m = (int)std::min<int64_t>(chunk, n - base);

@@ -31,7 +31,7 @@ struct TgtSrc {
 // Mechanism data the gate needs: thermo table [14][N] and 1/W [N].
 struct PostIn {
     const double *nasa_t, *invW;
-    double tau_T, y_min, margin, max_dT;
+    double tau_T, y_min, margin, max_dT, T_max;
 };
 
 int64_t surrogate_param_count();
@@ -54,6 +54,7 @@ struct Surrogate {
     uint16_t *X = nullptr, *XT = nullptr, *H[4] = {}, *HT[4] = {};
     float *Z[4] = {}, *out = nullptr, *Tg = nullptr, *dOf = nullptr, *dH = nullptr, *dZf = nullptr;
     uint16_t *dZ5 = nullptr, *dZ5T = nullptr, *dZb = nullptr, *dZbT = nullptr;
+    float *csum = nullptr;   // partial column sums of the bias gradients
     int *idx = nullptr;
 
     ~Surrogate();
@@ -64,6 +65,7 @@ struct Surrogate {
     int reserve_ws(int rows, bool training, char *err);
     void forward(int B, bool training, bool out_transposed, hipStream_t s);
     void backward(int B, hipStream_t s);
+    void colsum(const float *src, int B, int ncol, float *dst, hipStream_t s);
     int compute_norm(const FeatSrc &f, const TgtSrc &t, hipStream_t s, char *err);
     int train(const FeatSrc &f, const TgtSrc &t, int epochs, int B, double lr0, double lr1,
               uint64_t seed, float *loss_hist, int verbose, hipStream_t s, char *err);

@@ -48,7 +48,7 @@ def test_surrogate_defaults_without_gpu():
     assert tp.batch % 64 == 0 and tp.epochs >= 1 and tp.lr_max > tp.lr_min >= 0
     g = chem.GateParams()
     L.chem_default_gate_params(ctypes.byref(g))
-    assert g.tau_T == 0.5 and g.y_min == -1e-10 and g.margin == 0.01 and g.max_dT == 1.0
+    assert g.tau_T == 0.5 and g.y_min == -1e-10 and g.margin == 0.01 and g.max_dT == 1.0 and g.T_max == 1000.0
     assert L.chem_surrogate_train(None, 0, None, None, None, None, None, None,
                                   ctypes.byref(tp), None) == -1
     assert L.chem_surrogate_load(None, b"/nonexistent") == -1

@@ -30,7 +30,7 @@ def _step(c, S, mech, dt, surrogate):
     c.map_reference(S["T"], S["p"], S["Y"], Yf, Yo, 1e-4, flags=S["flags"], ref_index=S["ref"])
     if surrogate:
         c.integrate_surrogate(S["T"], S["p"], S["Y"], dt, S["flags"], S["ref"],
-                              gate=dict(tau_T=1e9, y_min=-1.0, max_dT=1e30), h=S["h"], cost=S["cost"],
+                              gate=dict(tau_T=1e9, y_min=-1.0, max_dT=1e30, T_max=1e30), h=S["h"], cost=S["cost"],
                               status=S["status"])
     else:
         c.integrate(S["T"], S["p"], S["Y"], dt, flags=S["flags"], ref_index=S["ref"], h=S["h"],

@@ -163,7 +163,7 @@ def test_projection_gate_and_fallback_match_oracle():
     flags = torch.zeros(n, dtype=torch.uint8, device="cuda")
     status = torch.full((n,), 255, dtype=torch.uint8, device="cuda")
     h = torch.zeros(n, dtype=torch.float64, device="cuda")
-    s = c.integrate_surrogate(T, p, Y, f.dt, flags, gate=dict(tau_T=tau, y_min=y_min, max_dT=1e30),
+    s = c.integrate_surrogate(T, p, Y, f.dt, flags, gate=dict(tau_T=tau, y_min=y_min, max_dT=1e30, T_max=1e30),
                               h=h, status=status, stats=True)
     torch.cuda.synchronize()
     fl, stt, Tg, Yg = host(flags), host(status), host(T), host(Y)
@@ -196,7 +196,8 @@ def test_projection_gate_and_fallback_match_oracle():
                                      max_dT=0.5 * abs(dT))[0]
     flags.zero_()
     s = c.integrate_surrogate(dev(f.T), p, dev(f.Y), f.dt, flags,
-                              gate=dict(tau_T=tau, y_min=y_min, max_dT=0.5 * abs(dT)), stats=True)
+                              gate=dict(tau_T=tau, y_min=y_min, max_dT=0.5 * abs(dT), T_max=1e30),
+                              stats=True)
     assert s["cells_surrogate"] == 0 and s["cells_integrated"] == n
 
 
@@ -219,7 +220,7 @@ def test_surrogate_leaves_mapped_and_reference_cells_alone():
         f0 = host(flags).copy()
         st = torch.zeros(n, dtype=torch.uint8, device="cuda")
         if use_sur:
-            s = c.integrate_surrogate(T, p, Y, f.dt, flags, ref, gate=dict(tau_T=1e9, y_min=-1.0, max_dT=1e30), status=st,
+            s = c.integrate_surrogate(T, p, Y, f.dt, flags, ref, gate=dict(tau_T=1e9, y_min=-1.0, max_dT=1e30, T_max=1e30), status=st,
                                       stats=True)
         else:
             s = c.integrate(T, p, Y, f.dt, flags=flags, ref_index=ref, status=st, stats=True)

@@ -147,6 +147,9 @@ def test_surrogate_cell_gate_and_conservation():
     ok3, T3, Y3 = oracle.surrogate_cell(o, P, f.p[i], T, Y, 1e-6, tau_T=1e9, y_min=-1.0, max_dT=0.0)
     dT_pred = abs(T1 - T)
     assert (not ok3 and T3 == T and np.array_equal(Y3, Y)) or dT_pred == 0.0
+    # a cell hotter than T_max is not offered
+    ok4, T4, Y4 = oracle.surrogate_cell(o, P, f.p[i], T, Y, 1e-6, tau_T=1e9, y_min=-1.0, T_max=T - 1.0)
+    assert not ok4 and T4 == T and np.array_equal(Y4, Y)
     # out-of-box input is rejected
     P2 = P.copy()
     base = P2.size - 6 * IN
