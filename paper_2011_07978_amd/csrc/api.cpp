@@ -299,6 +299,82 @@ static int setup_surrogate(chem_ctx *c) {
     return CHEM_OK;
 }
 
+// Device order of the reactions and of their species slots.  The reaction
+// pass gives one reaction to each of 64 lanes and scatters its rate of
+// progress with one LDS atomic per slot (r0, r1, p0, p1, p2); lanes of one
+// instruction that hit the same species are serialised.  Reactions are placed
+// greedily, busiest first, into the 64-wide group and slot permutation that
+// adds the least to the per-group, per-slot species counts.  Present species
+// stay in the leading slots (missing ones are skipped by the kernels).  Sums
+// change only by rounding order.
+struct RxnSlots {
+    int src;      // mechanism index
+    int sp[5];    // r0 r1 p0 p1 p2, -1 missing
+};
+static std::vector<RxnSlots> order_reactions(int N, int R, const int *rea, const int *pro) {
+    std::vector<int> freq(N, 0);
+    for (int j = 0; j < R; ++j) {
+        for (int s = 0; s < 2; ++s) if (rea[2 * j + s] >= 0) ++freq[rea[2 * j + s]];
+        for (int s = 0; s < 3; ++s) if (pro[3 * j + s] >= 0) ++freq[pro[3 * j + s]];
+    }
+    std::vector<int> byw(R);
+    for (int j = 0; j < R; ++j) byw[j] = j;
+    auto weight = [&](int j) {
+        int w = 0;
+        for (int s = 0; s < 2; ++s) if (rea[2 * j + s] >= 0) w += freq[rea[2 * j + s]];
+        for (int s = 0; s < 3; ++s) if (pro[3 * j + s] >= 0) w += freq[pro[3 * j + s]];
+        return w;
+    };
+    std::stable_sort(byw.begin(), byw.end(), [&](int a, int b) { return weight(a) > weight(b); });
+    const int nb = (R + 63) / 64;
+    std::vector<int> fill(nb, 0), cnt((size_t)nb * 5 * N, 0);
+    std::vector<std::vector<RxnSlots>> blocks(nb);
+    static const int perm3[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    for (int j : byw) {
+        int rs[2], nr = 0, ps[3], np = 0;
+        for (int s = 0; s < 2; ++s) if (rea[2 * j + s] >= 0) rs[nr++] = rea[2 * j + s];
+        for (int s = 0; s < 3; ++s) if (pro[3 * j + s] >= 0) ps[np++] = pro[3 * j + s];
+        long best = -1;
+        RxnSlots pick{};
+        int pick_b = -1;
+        for (int b = 0; b < nb; ++b) {
+            const int cap = std::min(64, R - 64 * b);
+            if (fill[b] >= cap) continue;
+            const int *cb = &cnt[(size_t)b * 5 * N];
+            for (int ir = 0; ir < (nr == 2 ? 2 : 1); ++ir) {
+                for (int ip = 0; ip < 6; ++ip) {
+                    bool ok = true;
+                    RxnSlots t{j, {-1, -1, -1, -1, -1}};
+                    for (int s = 0; s < nr; ++s) t.sp[s] = rs[(s + ir) % nr];
+                    for (int s = 0; s < np; ++s) {
+                        const int q = perm3[ip][s];
+                        if (q >= np) { ok = false; break; }
+                        t.sp[2 + s] = ps[q];
+                    }
+                    if (!ok) continue;
+                    long cost = 0;
+                    for (int s = 0; s < 5; ++s)
+                        if (t.sp[s] >= 0) cost += 2L * cb[s * N + t.sp[s]] + 1;
+                    // prefer the emptier group on ties, so groups fill evenly
+                    cost = cost * 128 + fill[b];
+                    if (best < 0 || cost < best) { best = cost; pick = t; pick_b = b; }
+                }
+            }
+        }
+        int *cb = &cnt[(size_t)pick_b * 5 * N];
+        for (int s = 0; s < 5; ++s) if (pick.sp[s] >= 0) ++cb[s * N + pick.sp[s]];
+        ++fill[pick_b];
+        blocks[pick_b].push_back(pick);
+    }
+    std::vector<RxnSlots> out;
+    out.reserve(R);
+    for (auto &bl : blocks) {
+        std::sort(bl.begin(), bl.end(), [](const RxnSlots &a, const RxnSlots &b) { return a.src < b.src; });
+        out.insert(out.end(), bl.begin(), bl.end());
+    }
+    return out;
+}
+
 int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
     if (!c || !m) return CHEM_E_INVALID_ARG;
     const int E = m->n_elements, N = m->n_species, R = m->n_reactions;
@@ -396,16 +472,17 @@ int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
     std::vector<RxnRec> rxn(R);
     std::vector<int> tb_ptr(1, 0), eff_sp;
     std::vector<double> eff_am1;
-    for (int j = 0; j < R; ++j) {
-        auto sl = [&](int k) { return k < 0 ? N : k; };
-        const int r0 = sl(m->reactants[2 * j]), r1 = sl(m->reactants[2 * j + 1]);
-        const int p0 = sl(m->products[3 * j]), p1 = sl(m->products[3 * j + 1]), p2 = sl(m->products[3 * j + 2]);
+    const std::vector<RxnSlots> ord = order_reactions(N, R, m->reactants, m->products);
+    for (int i = 0; i < R; ++i) {
+        const int j = ord[i].src;
+        auto sl = [&](int s) { return ord[i].sp[s] < 0 ? N : ord[i].sp[s]; };
+        const int r0 = sl(0), r1 = sl(1), p0 = sl(2), p1 = sl(3), p2 = sl(4);
         int snu = 0;
         for (int s = 0; s < 2; ++s) snu -= m->reactants[2 * j + s] >= 0;
         for (int s = 0; s < 3; ++s) snu += m->products[3 * j + s] >= 0;
         int tb = TB_NONE;
         int es[3] = {N, N, N};
-        RxnRec &q = rxn[j];
+        RxnRec &q = rxn[i];
         q.eff[0] = q.eff[1] = q.eff[2] = 0.0;
         if (is_tb[j]) {
             if (eff[j].size() <= 3) {
@@ -451,6 +528,7 @@ int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
     M.off_e = off; off += N;
     M.off_cp = off; off += N;
     M.off_tb = off; off += M.n;
+    M.off_sv = off; off += 128;   // triangular-solve results, by pivot step (2 x 64)
     M.lds_doubles = off;
     {
         std::vector<MechDev> one(1, M);

@@ -285,14 +285,17 @@ __device__ __forceinline__ bool lu_factor(double (&a)[NP], int &t, double &dinv,
     dinv = 0.0;
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
+        // Pivot search on the upper 32 bits of |a| (sign, exponent and 20
+        // mantissa bits): the chosen row is within a factor 1 + 2^-20 of the
+        // largest candidate, ties going to the lowest lane.  A NaN entry sorts
+        // above every number and is caught by the reciprocal check below.
         const bool cand = active && t < 0;
-        const double v = cand ? fabs(a[k]) : -1.0;
-        const double vmax = wave_max(v);
-        const unsigned long long bal = __ballot(cand && v == vmax);
-        // no candidate (NaN column): fall back to lane 0; detected below
+        const unsigned key = cand ? ((unsigned)__double2hiint(a[k]) & 0x7fffffffu) : 0u;
+        const unsigned kmax = wave_max_u32(key);
+        const unsigned long long bal = __ballot(cand && key == kmax);
         const int p = bal ? (int)__builtin_ctzll(bal) : 0;
         const double piv = readlane_d(a[k], p);
-        const double rinv = 1.0 / piv;
+        const double rinv = recip_nr(piv);
         if (lane == p) {
             t = k;
             dinv = rinv;
@@ -317,28 +320,63 @@ __device__ __forceinline__ bool lu_factor(double (&a)[NP], int &t, double &dinv,
     return !wave_any(bad);
 }
 
+// Solve with the factors of lu_factor.  Pivot step k's value is read from
+// lane pk[k] before that lane's own update at step k, so every lane updates
+// unconditionally: lanes whose value was already taken only accumulate terms
+// nobody reads.  The values taken (y_k forward, x_k backward) are kept in LDS
+// (sv, 2 x 64 doubles of this wavefront), written by lane 0 eight at a time;
+// lane k returns x_k.
 template <int NP>
 __device__ __forceinline__ double lu_solve(const double (&a)[NP], int t, const double dinv,
-                                           int pk, double b) {
-    // keep the pivot lookups and masks inside this call (not hoisted across
-    // calls, where they would hold ~3 NP scalar register pairs)
+                                           int pk, double b, double *sv) {
+    // keep the pivot lookups inside this call (not hoisted across calls, where
+    // they would hold ~NP scalar registers)
     asm volatile("" : "+v"(pk), "+v"(t));
+    const int lane = lane_id();
 #pragma unroll
-    for (int k = 0; k < NP; ++k) {
-        const int p = __builtin_amdgcn_readlane(pk, k);
-        const double yk = readlane_d(b, p);
-        if (t > k) b = fma(-a[k], yk, b);
-        if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);
-    }
+    for (int k0 = 0; k0 < NP; k0 += 8) {
+        double yv[8];
 #pragma unroll
-    for (int k = NP - 1; k >= 0; --k) {
-        const int p = __builtin_amdgcn_readlane(pk, k);
-        const double xk = readlane_d(b * dinv, p);
-        if (t < k) b = fma(-a[k], xk, b);
-        if (t == k) b = xk;
-        if ((k & 7) == 0) __builtin_amdgcn_sched_barrier(0);
+        for (int u = 0; u < 8; ++u) {
+            const int k = k0 + u;
+            if (k < NP) {
+                const int p = __builtin_amdgcn_readlane(pk, k);
+                yv[u] = readlane_d(b, p);
+                b = fma(-a[k], yv[u], b);
+            }
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (k0 + u < NP) sv[k0 + u] = yv[u];
+        }
+        __builtin_amdgcn_sched_barrier(0);
     }
-    return shfl_d(b, pk);
+    wave_sync();
+    b = sv[t >= 0 ? t : 0];
+#pragma unroll
+    for (int k0 = NP - 1; k0 >= 0; k0 -= 8) {
+        double xv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = k0 - u;
+            if (k >= 0) {
+                const int p = __builtin_amdgcn_readlane(pk, k);
+                xv[u] = readlane_d(b * dinv, p);
+                b = fma(-a[k], xv[u], b);
+            }
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (k0 - u >= 0) sv[64 + k0 - u] = xv[u];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    wave_sync();
+    const double x = lane < NP ? sv[64 + lane] : 0.0;
+    wave_sync();   // the next call overwrites sv
+    return x;
 }
 
 template <int NP>
@@ -391,7 +429,7 @@ __device__ __forceinline__ bool rodas_attempt(const MechDev *__restrict__ M, dou
             rv += (kRodasC[s][3] / h) * u3;
             rv += (kRodasC[s][4] / h) * u4;
         }
-        const double us = lu_solve<NP>(a, t, dinv, pk, rv);
+        const double us = lu_solve<NP>(a, t, dinv, pk, rv, lds + M->off_sv);
         u0 = s == 0 ? us : u0;
         u1 = s == 1 ? us : u1;
         u2 = s == 2 ? us : u2;

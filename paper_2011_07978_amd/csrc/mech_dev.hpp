@@ -47,7 +47,7 @@ struct MechDev {
     const int *eff_sp;
     const double *eff_am1;  // alpha - 1
     // LDS layout (offsets in doubles)
-    int off_J, off_q, off_C, off_g, off_h, off_e, off_cp, off_tb, lds_doubles;
+    int off_J, off_q, off_C, off_g, off_h, off_e, off_cp, off_tb, off_sv, lds_doubles;
 };
 
 struct IntParams {

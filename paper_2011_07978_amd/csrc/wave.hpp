@@ -62,6 +62,29 @@ __device__ __forceinline__ double wave_max(double v) {
     return max2(max2(readlane_d(v, 0), readlane_d(v, 16)), max2(readlane_d(v, 32), readlane_d(v, 48)));
 }
 
+// Maximum of unsigned 32-bit keys (every lane returns the same value).
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xf, 0xf, false));
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xf, 0xf, false));
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xf, 0xf, false));
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xf, 0xf, false));
+    const unsigned a = max((unsigned)__builtin_amdgcn_readlane((int)v, 0),
+                           (unsigned)__builtin_amdgcn_readlane((int)v, 16));
+    const unsigned b = max((unsigned)__builtin_amdgcn_readlane((int)v, 32),
+                           (unsigned)__builtin_amdgcn_readlane((int)v, 48));
+    return max(a, b);
+}
+
+// 1/x from the hardware reciprocal estimate refined by two Newton-Raphson
+// steps (r <- r + r (1 - x r)); zero, infinite and NaN x give NaN.
+__device__ __forceinline__ double recip_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 
 }  // namespace chem
