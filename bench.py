@@ -288,7 +288,13 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="surrogate", choices=["small", "flame", "mapped", "large",
-                                                             "surrogate"])
+                                                             "surrogate", "unit", "mapping-study"],
+                    help="unit: the load-balancing benchmark of Sec. 3 (layouts C1-C4); "
+                         "mapping-study: mapped vs unmapped error over Z_tol and the T criterion")
+    ap.add_argument("--unit-problems", type=int, default=100,
+                    help="unit benchmark: problems (cells) per slot")
+    ap.add_argument("--unit-reps", type=int, default=3)
+    ap.add_argument("--study-steps", type=int, default=10, help="mapping study: flow steps")
     ap.add_argument("--cells", type=int, default=0, help="override the field size")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -319,6 +325,38 @@ def main():
 
     from paper_2011_07978_amd import accounting, synth
     from paper_2011_07978_amd.chem import Chem
+
+    if args.workload in ("unit", "mapping-study"):
+        from paper_2011_07978_amd import studies
+        mech = synth.mechanism("mech53")
+        chem = Chem(0)
+        chem.set_mechanism(mech)
+        t0 = time.perf_counter()
+        if args.workload == "unit":
+            res = studies.unit_benchmark(chem, torch, synth, mech, n_per_slot=args.unit_problems,
+                                         reps=args.unit_reps, log=log)
+            line = {"metric": "chi_su = tau_unbalanced / tau_balanced (Sec. 3 unit benchmark)",
+                    "value": res["layouts"]["C1"]["chi_su"], "unit": "ratio",
+                    "higher_is_better": True, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+                    "config": {"workload": f"unit benchmark: {res['slots']} slots x "
+                                           f"{args.unit_problems} problems, heavy/light "
+                                           "pseudo-problems, 53 species / 325 reactions",
+                               "parallelism": "single GPU"},
+                    "unit_benchmark": res}
+        else:
+            res = studies.mapping_study(chem, torch, synth, mech,
+                                        n_cells=args.cells or 262144, steps=args.study_steps, log=log)
+            best = [r for r in res["runs"] if r["Z_tol"] == 1e-4 and not r["use_T"]][0]
+            line = {"metric": "mean |dT| of the mapped path vs unmapped (Z_tol 1e-4)",
+                    "value": best["mean_abs_dT"], "unit": "K", "higher_is_better": False,
+                    "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+                    "config": {"workload": f"mapping study: {res['cells']} cells, {res['steps']} "
+                                           "flow steps, 53 species / 325 reactions",
+                               "parallelism": "single GPU"},
+                    "mapping_study": res}
+        line["wall_s"] = time.perf_counter() - t0
+        print(json.dumps(line), flush=True)
+        return
 
     wl = synth.WORKLOADS[args.workload]
     mech = synth.mechanism(wl["mech"])
@@ -387,7 +425,7 @@ def main():
     # (profiles/k_integrate_queue_54__pmc_traffic_mapped_262k.md)
     traffic = None
     if kname == "k_integrate_queue" and mech.n_species == 53:
-        traffic = 8633.0 * float(np.mean([s["cells_integrated"] for s in st_h]))
+        traffic = 8588.0 * float(np.mean([s["cells_integrated"] for s in st_h]))
     roof = dict(bound="alu", achieved=achieved, peak=accounting.FP64_VECTOR_PEAK_TFLOPS,
                 unit="TFLOP/s", frac=achieved / accounting.FP64_VECTOR_PEAK_TFLOPS, traffic=traffic,
                 traffic_unit="bytes per launch" if traffic else None,

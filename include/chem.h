@@ -69,7 +69,10 @@ enum {
 /* scheduling of cells onto wavefronts */
 enum {
     CHEM_SCHED_PLAIN = 0,  /* one static launch, cell i on workgroup i */
-    CHEM_SCHED_QUEUE = 1   /* persistent kernel, atomic work queue + stealing */
+    CHEM_SCHED_QUEUE = 1,  /* persistent kernel, atomic work queue + stealing */
+    CHEM_SCHED_BLOCKS = 2  /* persistent kernel, slot s owns one contiguous block of
+                              cells (static partition, the unbalanced baseline of
+                              the load-balancing benchmark, Sec. 3) */
 };
 
 typedef struct chem_ctx chem_ctx;
@@ -104,7 +107,7 @@ typedef struct {
     double atol;          /* absolute tolerance (default 1e-12) */
     int32_t max_steps;    /* attempted-step limit per cell and call (default 100000) */
     double hmin_frac;     /* fail when h < hmin_frac * dt (default 1e-14) */
-    int32_t schedule;     /* CHEM_SCHED_PLAIN or CHEM_SCHED_QUEUE (default QUEUE) */
+    int32_t schedule;     /* CHEM_SCHED_PLAIN, _QUEUE or _BLOCKS (default QUEUE) */
     int32_t queue_chunk;  /* cells per atomic grab; 0 = tuned value (default 0) */
     int32_t slots_per_cu; /* persistent workgroups per CU; 0 = tuned value */
     int32_t order_by_cost;/* 1: heavy-first queue order from `cost` (default 1) */
@@ -215,6 +218,15 @@ int chem_max_species(void);
 int chem_set_options(chem_ctx *ctx, const chem_options *o);
 int chem_get_options(const chem_ctx *ctx, chem_options *o);
 void chem_default_options(chem_options *o);
+
+/* Number of cells integrated at once by the persistent launches
+ * (CHEM_SCHED_QUEUE and CHEM_SCHED_BLOCKS) for the current mechanism and
+ * options, before capping by the cell count: CUs x workgroups per CU x cells
+ * per workgroup (wavefronts per workgroup for up to 63 species, 1 above).
+ * Under CHEM_SCHED_BLOCKS slot s owns cells [s B, (s + 1) B) with
+ * B = ceil(n_cells / min(slots, n_cells)).  These slots play the role of the processes of the paper's load-balancing
+ * benchmark (Sec. 3).  Requires a mechanism (CHEM_E_INVALID_ARG otherwise). */
+int chem_query_slots(const chem_ctx *ctx, int64_t *slots);
 
 /* Preallocate workspace for up to max_cells cells so that later calls with
  * n_cells <= max_cells allocate nothing (required before stream capture). */

@@ -15,7 +15,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libchem.so")
 
-CHEM_SCHED_PLAIN, CHEM_SCHED_QUEUE = 0, 1
+CHEM_SCHED_PLAIN, CHEM_SCHED_QUEUE, CHEM_SCHED_BLOCKS = 0, 1, 2
 (CELL_OK, CELL_MAX_STEPS, CELL_H_UNDERFLOW, CELL_NONFINITE, CELL_BAD_INPUT, CELL_MAPPED,
  CELL_SURROGATE) = range(7)
 FLAG_SOLVE, FLAG_REFERENCE, FLAG_MAPPED, FLAG_SURROGATE = range(4)
@@ -72,6 +72,7 @@ class TuneEntry(C.Structure):
 
 EXPORTS = ["chem_create", "chem_destroy", "chem_set_stream", "chem_last_error",
            "chem_set_mechanism", "chem_max_species", "chem_set_options", "chem_get_options",
+           "chem_query_slots",
            "chem_default_options", "chem_reserve", "chem_map_reference", "chem_integrate",
            "chem_eval_rhs_jac", "chem_rodas_step", "chem_integrate_surrogate",
            "chem_default_train_params", "chem_default_gate_params", "chem_surrogate_param_count",
@@ -104,6 +105,7 @@ def load_library(path: str = LIB_PATH):
     L.chem_max_species.argtypes = []
     L.chem_set_options.argtypes = [vp, C.POINTER(Options)]
     L.chem_get_options.argtypes = [vp, C.POINTER(Options)]
+    L.chem_query_slots.argtypes = [vp, C.POINTER(C.c_int64)]
     L.chem_default_options.argtypes = [C.POINTER(Options)]
     L.chem_default_options.restype = None
     L.chem_reserve.argtypes = [vp, C.c_int64]
@@ -226,6 +228,12 @@ class Chem:
 
     def reserve(self, max_cells: int):
         self._check(self.L.chem_reserve(self.h, int(max_cells)), "chem_reserve")
+
+    def slots(self) -> int:
+        """Cells integrated at once by the persistent launches (see chem_query_slots)."""
+        v = C.c_int64(0)
+        self._check(self.L.chem_query_slots(self.h, C.byref(v)), "chem_query_slots")
+        return int(v.value)
 
     # ------------------------------------------------------------ hot path
     def map_reference(self, T, p, Y, Y_fuel, Y_ox, Z_tol, T_tol=1.0, use_T=False,

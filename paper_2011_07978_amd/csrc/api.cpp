@@ -215,7 +215,8 @@ const char *chem_last_error(const chem_ctx *c) { return c ? c->err.c_str() : "nu
 int chem_set_options(chem_ctx *c, const chem_options *o) {
     if (!c || !o) return CHEM_E_INVALID_ARG;
     if (!(o->rtol > 0.0) || !(o->atol > 0.0) || o->max_steps < 1 || !(o->hmin_frac >= 0.0) ||
-        !(o->hmin_frac < 1.0) || (o->schedule != CHEM_SCHED_PLAIN && o->schedule != CHEM_SCHED_QUEUE) ||
+        !(o->hmin_frac < 1.0) || (o->schedule != CHEM_SCHED_PLAIN && o->schedule != CHEM_SCHED_QUEUE &&
+         o->schedule != CHEM_SCHED_BLOCKS) ||
         o->queue_chunk < 0 || o->queue_chunk > 4096 || o->slots_per_cu < 0 || o->slots_per_cu > 64)
         return fail(c, CHEM_E_INVALID_ARG, "invalid options");
     c->opt = *o;
@@ -225,6 +226,18 @@ int chem_set_options(chem_ctx *c, const chem_options *o) {
 int chem_get_options(const chem_ctx *c, chem_options *o) {
     if (!c || !o) return CHEM_E_INVALID_ARG;
     *o = c->opt;
+    return CHEM_OK;
+}
+
+int chem_query_slots(const chem_ctx *c, int64_t *slots) {
+    if (!c || !slots || !c->has_mech) return CHEM_E_INVALID_ARG;
+    if (c->big) {
+        const int per_cu = c->opt.slots_per_cu > 0 ? std::min(c->opt.slots_per_cu, c->occ) : c->occ;
+        *slots = (int64_t)c->num_cu * per_cu;
+    } else {
+        const int per_cu = c->opt.slots_per_cu > 0 ? c->opt.slots_per_cu : std::max(1, c->occ);
+        *slots = (int64_t)c->num_cu * per_cu * wave_kernel_wpb(c->M);
+    }
     return CHEM_OK;
 }
 
@@ -725,6 +738,13 @@ static int integrate_core(chem_ctx *c, int64_t n, double *T, const double *p, do
             P.seg_ctr = seg;
             P.n_active = nact;
             P.chunk = c->opt.queue_chunk > 0 ? c->opt.queue_chunk : 1;
+            if (!c->big) {
+                const int slots = c->opt.slots_per_cu > 0 ? c->opt.slots_per_cu : std::max(1, c->occ);
+                grid = c->num_cu * slots;
+                if (grid > n) grid = (int)n;
+            }
+        } else if (c->opt.schedule == CHEM_SCHED_BLOCKS) {
+            P.block_static = 1;
             if (!c->big) {
                 const int slots = c->opt.slots_per_cu > 0 ? c->opt.slots_per_cu : std::max(1, c->occ);
                 grid = c->num_cu * slots;

@@ -574,27 +574,48 @@ __global__ __launch_bounds__(64) void k_integrate_plain(const MechDev *__restric
 template <int NP>
 __global__ __launch_bounds__(256) void k_integrate_queue(const MechDev *__restrict__ M, IntParams P) {
     double *lds = init_lds<true>(M);
-    const int nact = uniform_i(*P.n_active);
+    const int wpb = (int)(blockDim.x >> 6);
+    const int wave = (int)blockIdx.x * wpb + (int)(threadIdx.x >> 6);
+    // P.block_static: wavefront w owns cells [w B, (w + 1) B) and integrates
+    // them in index order (static partition, no balancing); otherwise cells
+    // come from the work queue in chunks, segment by segment with stealing.
+    const bool stat = P.block_static != 0;
+    int64_t sb = 0, se = 0;
+    if (stat) {
+        const int64_t nw = (int64_t)gridDim.x * wpb;
+        const int64_t B = (P.ncells + nw - 1) / nw;
+        sb = wave * B;
+        se = sb + B < P.ncells ? sb + B : P.ncells;
+    }
+    const int nact = stat ? 0 : uniform_i(*P.n_active);
     const int chunk = P.chunk;
-    int seg = (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % NSEG);
-    int probes = 0;
-    while (probes < NSEG) {
-        int c = 0;
-        if (lane_id() == 0) c = atomicAdd(&P.seg_ctr[seg], chunk);
-        c = uniform_i(__shfl(c, 0));
-        const int first = seg + NSEG * c;
-        if (first >= nact) {
-            seg = seg + 1 == NSEG ? 0 : seg + 1;
-            ++probes;
-            continue;
+    int seg = wave % NSEG;
+    int first = 0, q = chunk;
+    while (true) {
+        int64_t cell;
+        if (stat) {
+            if (sb >= se) break;
+            cell = sb++;
+            if (P.flags && P.flags[cell] >= 2) continue;
+        } else {
+            if (q >= chunk || first + NSEG * q >= nact) {
+                bool got = false;
+                for (int probes = 0; probes < NSEG;) {
+                    int c = 0;
+                    if (lane_id() == 0) c = atomicAdd(&P.seg_ctr[seg], chunk);
+                    c = uniform_i(__shfl(c, 0));
+                    first = seg + NSEG * c;
+                    if (first < nact) { got = true; break; }
+                    seg = seg + 1 == NSEG ? 0 : seg + 1;
+                    ++probes;
+                }
+                if (!got) break;
+                q = 0;
+            }
+            cell = P.queue[first + NSEG * q];
+            ++q;
         }
-        probes = 0;
-        for (int q = 0; q < chunk; ++q) {
-            const int pos = first + NSEG * q;
-            if (pos >= nact) break;
-            const int64_t cell = P.queue[pos];
-            integrate_cell<NP, true>(M, P, cell, lds);
-        }
+        integrate_cell<NP, true>(M, P, cell, lds);
     }
 }
 

@@ -602,7 +602,12 @@ __global__ __launch_bounds__(BT) void k_big_plain(const MechDev *__restrict__ M,
     const BigLds L = big_layout(M->n, lds);
     init_big(L);
     double *Jg = jws + (size_t)blockIdx.x * M->n * M->n;
-    for (int64_t cell = blockIdx.x; cell < P.ncells; cell += gridDim.x) {
+    // round robin over the slots, or (block_static) one contiguous block each
+    const int64_t B = (P.ncells + gridDim.x - 1) / gridDim.x;
+    const int64_t c0 = P.block_static ? blockIdx.x * B : blockIdx.x;
+    const int64_t c1 = P.block_static ? (c0 + B < P.ncells ? c0 + B : P.ncells) : P.ncells;
+    const int64_t stride = P.block_static ? 1 : gridDim.x;
+    for (int64_t cell = c0; cell < c1; cell += stride) {
         if (P.flags && P.flags[cell] >= 2) continue;
         integrate_cell_big(M, P, cell, L, Jg);
     }
@@ -703,7 +708,7 @@ hipError_t big_prepare(int n) {
 hipError_t launch_integrate_big(const MechDev &M, const MechDev *Md, const IntParams &P,
                                 int schedule, int grid, double *jws, hipStream_t s) {
     const size_t sh = big_lds_bytes(M.n);
-    if (schedule == 0)
+    if (schedule != 1)   // plain round robin, or static blocks (P.block_static)
         hipLaunchKernelGGL(k_big_plain, dim3((unsigned)grid), dim3(BT), sh, s, Md, P, jws);
     else
         hipLaunchKernelGGL(k_big_queue, dim3((unsigned)grid), dim3(BT), sh, s, Md, P, jws);

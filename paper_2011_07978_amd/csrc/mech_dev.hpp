@@ -67,6 +67,7 @@ struct IntParams {
     int *seg_ctr;           // [NSEG] consumed items per segment
     const int *n_active;    // device scalar
     int chunk;
+    int block_static;       // persistent launch, contiguous block of cells per slot
     unsigned long long *stats;  // [8] device counters
 };
 

@@ -367,6 +367,35 @@ def field_mapped(n_cells=262144, seed=103, mech_name="mech53", n_steps=10) -> Fi
                  1e-6, n_steps, cls[perm], ("cold", "mixing", "igniting"))
 
 
+# Load-balancing benchmark (Sec. 3): a fraction x of the processes (here the
+# persistent slots) holds heavy problems at ratio theta; the rest hold light
+# problems only; heavy problems are 1/5 of all problems in every layout.
+UNIT_LAYOUTS = {"C1": (0.2, 1.0), "C2": (0.25, 0.8), "C3": (0.5, 0.4), "C4": (1.0, 0.2)}
+
+
+def field_unit(layout, heavy, light, n_slots, n_per_slot, dt=1e-6):
+    """Heavy/light pseudo-problem field: slot s owns cells [s B, (s + 1) B),
+    B = n_per_slot; the first round(x n_slots) slots start with
+    round(theta B) copies of the heavy problem, every other cell is a copy of
+    the light problem.  heavy and light are (T, p, Y[N], h) tuples.  Returns
+    (Field, h, is_heavy)."""
+    x, theta = UNIT_LAYOUTS[layout]
+    n = n_slots * n_per_slot
+    is_heavy = np.zeros(n, bool)
+    n_theta = int(round(x * n_slots))
+    n_heavy = int(round(theta * n_per_slot))
+    for s in range(n_theta):
+        is_heavy[s * n_per_slot: s * n_per_slot + n_heavy] = True
+    pick = lambda a, b: np.where(is_heavy, a, b)
+    T = pick(heavy[0], light[0]).astype(np.float64)
+    p = pick(heavy[1], light[1]).astype(np.float64)
+    Y = np.where(is_heavy[None, :], np.asarray(heavy[2])[:, None], np.asarray(light[2])[:, None])
+    h = pick(heavy[3], light[3]).astype(np.float64)
+    f = Field(T, p, np.ascontiguousarray(Y, dtype=np.float64), dt, 1,
+              is_heavy.astype(np.int8), ("light", "heavy"))
+    return f, h, is_heavy
+
+
 WORKLOADS = {
     "small": dict(mech="small", field=lambda n=4096: field_small(n)),
     "flame": dict(mech="mech53", field=lambda n=65536: field_bimodal("mech53", n, 102)),

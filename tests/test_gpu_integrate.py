@@ -10,7 +10,7 @@ torch = pytest.importorskip("torch")
 
 from oracle import Oracle  # noqa: E402
 from paper_2011_07978_amd import synth  # noqa: E402
-from paper_2011_07978_amd.chem import CHEM_SCHED_PLAIN, CHEM_SCHED_QUEUE  # noqa: E402
+from paper_2011_07978_amd.chem import CHEM_SCHED_BLOCKS, CHEM_SCHED_PLAIN, CHEM_SCHED_QUEUE  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -75,13 +75,15 @@ def test_flame_cells_match_oracle(flame_case):
 
 def test_plain_and_queue_bitwise_identical():
     """Paper App. A: balancing without mapping gives results identical to the
-    standard model.  Here: the queue launch equals the static launch bit for bit."""
+    standard model.  Here: the queue launch equals the static launches (one
+    cell per workgroup, and one contiguous block per slot) bit for bit."""
     from tests.gpu_util import chem_for, dev, host, say
     mech = synth.mechanism("mech53")
     f = synth.field_bimodal("mech53", 4096, seed=77, shuffle=True)
     c = chem_for(mech)
     outs = []
-    for sched, chunk in ((CHEM_SCHED_PLAIN, 0), (CHEM_SCHED_QUEUE, 1), (CHEM_SCHED_QUEUE, 4)):
+    for sched, chunk in ((CHEM_SCHED_PLAIN, 0), (CHEM_SCHED_QUEUE, 1), (CHEM_SCHED_QUEUE, 4),
+                         (CHEM_SCHED_BLOCKS, 0)):
         say("bitwise", sched, chunk)
         c.set_options(schedule=sched, queue_chunk=chunk)
         T, Y = dev(f.T), dev(f.Y)
@@ -95,6 +97,23 @@ def test_plain_and_queue_bitwise_identical():
     for T, Y in outs[1:]:
         assert np.array_equal(T, outs[0][0])
         assert np.array_equal(Y, outs[0][1])
+
+
+def test_static_blocks_cover_every_cell_once():
+    """The static-partition launch (each slot owns a contiguous block) integrates
+    every non-mapped cell exactly once, also when the cell count is not a
+    multiple of the slot count and when there are fewer cells than slots."""
+    from tests.gpu_util import chem_for, run_integrate, say
+    mech = synth.mechanism("small")
+    for n in (5000, 37, 1):
+        f = synth.field_small(n)
+        c = chem_for(mech, schedule=CHEM_SCHED_BLOCKS)
+        say("static blocks", n)
+        out = run_integrate(c, f)
+        assert out["stats"]["cells_integrated"] == n
+        assert np.array_equal(out["cost"].cpu().numpy(), out["nacc"] + out["nrej"])
+        ref = run_integrate(chem_for(mech, schedule=CHEM_SCHED_QUEUE), f)
+        assert np.array_equal(out["T"], ref["T"]) and np.array_equal(out["Y"], ref["Y"])
 
 
 def test_every_cell_processed_once_and_cost_feedback():
@@ -198,3 +217,38 @@ def test_mapped_step_matches_oracle():
     assert rep["ok"], rep
     assert s["cells_mapped"] == int((flags_o == 2).sum())
     assert np.all(host(st)[flags_o == 2] == 5)
+
+
+def test_full_size_field_sampled_parity():
+    """The 1,048,576-cell field of the headline workload, mapped (Z_tol 1e-4)
+    and integrated in the launch configuration the benchmark times (heavy-first
+    work queue); a stratified sample of cells is recomputed by the oracle one
+    by one: integrated cells from their own state, mapped cells from the
+    reference cell's increment (Sec. 2.3)."""
+    from tests.gpu_util import chem_for, compare_to_oracle, dev, host, say
+    mech = synth.mechanism("mech53")
+    full = synth.WORKLOADS["surrogate"]["field"]()
+    assert full.n_cells == 1048576
+    Yf, Yo = synth.stream_fuel(mech), synth.stream_oxidiser(mech)
+    c = chem_for(mech, schedule=CHEM_SCHED_QUEUE)
+    say("full-size field", full.n_cells)
+    T, p, Y = dev(full.T), dev(full.p), dev(full.Y)
+    flags, ref = c.map_reference(T, p, Y, Yf, Yo, 1e-4)
+    s = c.integrate(T, p, Y, full.dt, flags=flags, ref_index=ref, stats=True)
+    torch.cuda.synchronize()
+    fl, r0 = host(flags), int(host(ref)[0])
+    assert r0 >= 0 and s["cells_failed"] == 0
+    assert s["cells_mapped"] + s["cells_integrated"] == full.n_cells
+    idx = synth.stratified_indices(full, 24, seed=11)
+    idx = idx[idx != r0]
+    sub = synth.subsample(full, np.concatenate([[r0], idx]))
+    sub_flags = np.concatenate([[1], fl[idx]]).astype(np.uint8)
+    o = Oracle(mech)
+    say("oracle on", sub.n_cells, "sampled cells")
+    refo = o.step_mapped(sub.T, sub.p, sub.Y, sub.dt, sub_flags, 0, threads=16)
+    keep = np.concatenate([[r0], idx])
+    out = dict(T=host(T)[keep], Y=host(Y)[:, keep])
+    rep = compare_to_oracle(out, refo[0], refo[1])
+    print(rep, s, "mapped in sample", int((sub_flags == 2).sum()))
+    assert rep["ok"], rep
+    assert (sub_flags == 2).sum() > 0 and (sub_flags == 0).sum() > 0
