@@ -272,10 +272,54 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
 }
 
 // -----------------------------------------------------------------------------
+// Dense linear algebra of the Rodas stages, one matrix row per lane.
+// -----------------------------------------------------------------------------
+// Pivot search for one column, cut into stages that the LU interleaves with
+// the previous step's trailing update (lookahead), so that the search's
+// dependent chain overlaps independent work.  The search compares the upper
+// 32 bits of |a| (sign, exponent and 20 mantissa bits): the chosen row is
+// within a factor 1 + 2^-20 of the largest candidate, ties going to the
+// lowest lane.  A NaN entry sorts above every number and is caught by the
+// reciprocal check after the factorisation.
+struct PivotSearch {
+    unsigned key, v;
+    int p;
+    double piv, r, e;
+    __device__ __forceinline__ void stage(int s, double col, bool cand) {
+        switch (s) {
+            case 0:
+                key = cand ? ((unsigned)__double2hiint(col) & 0x7fffffffu) : 0u;
+                v = max(key, (unsigned)__builtin_amdgcn_update_dpp(0, (int)key, 0xB1, 0xf, 0xf, false));
+                break;
+            case 1: v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xf, 0xf, false)); break;
+            case 2: v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xf, 0xf, false)); break;
+            case 3: v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xf, 0xf, false)); break;
+            case 4: {
+                const unsigned a = max((unsigned)__builtin_amdgcn_readlane((int)v, 0),
+                                       (unsigned)__builtin_amdgcn_readlane((int)v, 16));
+                const unsigned b = max((unsigned)__builtin_amdgcn_readlane((int)v, 32),
+                                       (unsigned)__builtin_amdgcn_readlane((int)v, 48));
+                v = max(a, b);
+                break;
+            }
+            case 5: {
+                const unsigned long long bal = __ballot(cand && key == v);
+                p = bal ? (int)__builtin_ctzll(bal) : 0;
+                break;
+            }
+            case 6: piv = readlane_d(col, p); break;
+            case 7: r = __builtin_amdgcn_rcp(piv); e = fma(-piv, r, 1.0); break;
+            case 8: r = fma(r, e, r); e = fma(-piv, r, 1.0); break;
+            default: r = fma(r, e, r); break;   // 1/piv: estimate + two Newton-Raphson steps
+        }
+    }
+};
+constexpr int kSearchStages = 10;
+constexpr int kColsPerStage = 4;
+
 // LU with partial pivoting, row-per-lane.  On return lane r holds its row of
 // L (columns before its pivot step t) and U (columns from t on); dinv = 1/U_tt;
 // lane k holds pk = the lane that became pivot at step k.
-// -----------------------------------------------------------------------------
 template <int NP>
 __device__ __forceinline__ bool lu_factor(double (&a)[NP], int &t, double &dinv, int &pk) {
     int lane = lane_id();
@@ -283,19 +327,13 @@ __device__ __forceinline__ bool lu_factor(double (&a)[NP], int &t, double &dinv,
     const bool active = lane < NP;
     t = -1;
     dinv = 0.0;
+    PivotSearch ps;
+#pragma unroll
+    for (int s = 0; s < kSearchStages; ++s) ps.stage(s, a[0], active);
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-        // Pivot search on the upper 32 bits of |a| (sign, exponent and 20
-        // mantissa bits): the chosen row is within a factor 1 + 2^-20 of the
-        // largest candidate, ties going to the lowest lane.  A NaN entry sorts
-        // above every number and is caught by the reciprocal check below.
-        const bool cand = active && t < 0;
-        const unsigned key = cand ? ((unsigned)__double2hiint(a[k]) & 0x7fffffffu) : 0u;
-        const unsigned kmax = wave_max_u32(key);
-        const unsigned long long bal = __ballot(cand && key == kmax);
-        const int p = bal ? (int)__builtin_ctzll(bal) : 0;
-        const double piv = readlane_d(a[k], p);
-        const double rinv = recip_nr(piv);
+        const int p = ps.p;
+        const double rinv = ps.r;
         if (lane == p) {
             t = k;
             dinv = rinv;
@@ -303,17 +341,28 @@ __device__ __forceinline__ bool lu_factor(double (&a)[NP], int &t, double &dinv,
         const bool upd = active && t < 0;
         const double l = upd ? a[k] * rinv : 0.0;
         if (upd) a[k] = l;
+        // column k + 1 first: the next pivot search starts from it and runs
+        // in stages between groups of the remaining column updates
+        int stage = 0;
 #pragma unroll
         for (int j = k + 1; j < NP; ++j) {
             const double pj = readlane_d(a[j], p);
             a[j] = fma(-l, pj, a[j]);
-            // bound how many broadcast values the scheduler keeps in flight
-            if (((j - k) & 7) == 0) __builtin_amdgcn_sched_barrier(0);
+            if (j == k + 1 || (j - k - 1) % kColsPerStage == 0) {
+                if (stage < kSearchStages) ps.stage(stage, a[k + 1], upd);
+                ++stage;
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        if (k + 1 < NP) {
+#pragma unroll
+            for (int s = 0; s < kSearchStages; ++s)
+                if (s >= stage) ps.stage(s, a[k + 1], upd);
         }
         __builtin_amdgcn_sched_barrier(0);
     }
-    // singular (zero pivot -> infinite reciprocal), NaN pivots, or a lane
-    // chosen twice (some row never became pivot)
+    // singular (zero pivot -> infinite reciprocal), NaN pivots, or an active
+    // row that never became pivot
     const bool bad = active && (t < 0 || !(fabs(dinv) < INFINITY));
     const int dst = active && t >= 0 ? t : lane;
     pk = __builtin_amdgcn_ds_permute(dst << 2, lane);
