@@ -454,6 +454,129 @@ __global__ __launch_bounds__(256) void k_surrogate_post(FeatSrc f, int64_t base,
     }
 }
 
+// ------------------------------------------------------ fused inference ----
+// Rows offered to the surrogate (no flag, T <= T_max): their chunk positions,
+// in any order, and their count (zeroed by k_zero_int first).
+__global__ void k_zero_int(int *p) { if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0; }
+
+__global__ __launch_bounds__(256) void k_sur_select(const uint8_t *flags, const double *T, int64_t base,
+                                                    int m, double T_max, int *idx, int *cnt) {
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    bool sel = false;
+    if (r < m) {
+        const int64_t i = base + r;
+        sel = (!flags || flags[i] == 0) && T[i] <= T_max;
+    }
+    const unsigned long long b = __ballot(sel);
+    const int lane = threadIdx.x & 63;
+    int off = 0;
+    if (lane == 0 && b) off = atomicAdd(cnt, __popcll(b));
+    off = __shfl(off, 0);
+    if (sel) idx[off + __popcll(b & ((1ull << lane) - 1ull))] = r;
+}
+
+// The whole network for a tile of 64 selected rows in one workgroup: the
+// input tile and the hidden activations stay in LDS (bf16), weights stream
+// from L2.  Per layer, wavefront w computes output columns [64w, 64w + 64)
+// (16 of the 64 outputs in the last layer) for all 64 rows with 16x16x32
+// MFMA blocks, accumulating over k in the same order as k_gemm_nt, so the
+// outputs equal the layer-by-layer path bit for bit.  Output row r goes to
+// outT[c][r] (r = chunk position), as the acceptance kernel reads it.
+constexpr int FT = 64;             // rows per tile
+constexpr int XLD = S_IN + 8;      // LDS row strides (bf16), padded against bank conflicts
+constexpr int HLD = S_HID + 8;
+struct MlpW {
+    const uint16_t *W[5];
+    const float *b[5];
+};
+
+template <int K, int NB>
+__device__ __forceinline__ void tile_layer(const uint16_t *In, int ldi, const uint16_t *__restrict__ W,
+                                           int n0, f32x4 (&acc)[4][NB]) {
+    const int lane = threadIdx.x & 63;
+    const int r16 = lane & 15, kq = (lane >> 4) * 8;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        bf16x8 a[4], b[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+            b[j] = *(const bf16x8 *)(W + (size_t)(n0 + 16 * j + r16) * K + k0 + kq);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = *(const bf16x8 *)(In + (16 * i + r16) * ldi + k0 + kq);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void hidden_layer(const uint16_t *In, int ldi, const uint16_t *W,
+                                             const float *bias, uint16_t *Out) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int n0 = 64 * w;
+    f32x4 acc[4][4];
+    tile_layer<K, 4>(In, ldi, W, n0, acc);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = n0 + 16 * j + (lane & 15);
+            const float bc = bias[col];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * i + 4 * (lane >> 4) + r;
+                Out[row * HLD + col] = f2bf(gelu_f(acc[i][j][r] + bc));
+            }
+        }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_infer(FeatSrc f, int64_t base, int m, const int *idx,
+                                                   const int *cnt, const float *norm, MlpW wt,
+                                                   float *outT) {
+    extern __shared__ uint16_t sm16[];
+    uint16_t *Xs = sm16, *Ha = Xs + FT * XLD, *Hb = Ha + FT * HLD;
+    const int n_sel = *cnt;
+    const int t0 = blockIdx.x * FT;
+    if (t0 >= n_sel) return;                       // whole workgroup
+    const int rows = n_sel - t0 < FT ? n_sel - t0 : FT;
+    const int tid = threadIdx.x, c = tid & 63;
+    const int nfeat = f.N + 3;
+    for (int rr = tid >> 6; rr < FT; rr += 4) {
+        uint16_t v = 0;
+        if (rr < rows && c < nfeat)
+            v = f2bf((float)((raw_feature(f, base + idx[t0 + rr], c) - norm[c]) / norm[64 + c]));
+        Xs[rr * XLD + c] = v;
+    }
+    __syncthreads();
+    hidden_layer<S_IN>(Xs, XLD, wt.W[0], wt.b[0], Ha);
+    __syncthreads();
+    hidden_layer<S_HID>(Ha, HLD, wt.W[1], wt.b[1], Hb);
+    __syncthreads();
+    hidden_layer<S_HID>(Hb, HLD, wt.W[2], wt.b[2], Ha);
+    __syncthreads();
+    hidden_layer<S_HID>(Ha, HLD, wt.W[3], wt.b[3], Hb);
+    __syncthreads();
+    const int lane = tid & 63, w = tid >> 6;
+    f32x4 acc[4][1];
+    tile_layer<S_HID, 1>(Hb, HLD, wt.W[4], 16 * w, acc);
+    const int col = 16 * w + (lane & 15);
+    const float bc = wt.b[4][col];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * i + 4 * (lane >> 4) + r;
+            if (row < rows) outT[(size_t)col * m + idx[t0 + row]] = acc[i][0][r] + bc;
+        }
+}
+static constexpr size_t kInferLds = sizeof(uint16_t) * (size_t)FT * (XLD + 2 * HLD);
+
 static void launch_post(int nel, dim3 g, hipStream_t s, const FeatSrc &f, int64_t base, int m,
                         const float *outT, const PostParams &q, double *T, double *Y, uint8_t *flags,
                         unsigned long long *stats) {
@@ -506,6 +629,8 @@ Surrogate::~Surrogate() {
 int Surrogate::init(int N_, int nel_, const std::vector<double> &E_host, char *err) {
     N = N_;
     nel = nel_;
+    SCHK(hipFuncSetAttribute((const void *)k_mlp_infer, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)kInferLds));
     const int64_t np = surrogate_param_count();
     float *fp = nullptr;
     SCHK(dalloc(&fp, np)); bufs.push_back(fp); P = fp;
@@ -577,6 +702,7 @@ int Surrogate::reserve_ws(int B, bool training, char *err) {
     }
     int *ip = nullptr;
     SCHK(dalloc(&ip, (size_t)B)); ws.push_back(ip); idx = ip;
+    SCHK(dalloc(&ip, (size_t)1)); ws.push_back(ip); sel_cnt = ip;
     ws_rows = B;
     ws_training = training;
     return 0;
@@ -799,6 +925,11 @@ int Surrogate::apply(const FeatSrc &f, double *T, double *Y, uint8_t *flags, con
     const int chunk = 262144;
     int rc = reserve_ws((int)std::min<int64_t>(n, chunk), false, err);
     if (rc) return rc;
+    MlpW wts{};
+    for (int l = 0; l < 5; ++l) {
+        wts.W[l] = Wb[l];
+        wts.b[l] = P + layer_offset(l) + (int64_t)layer_out(l) * layer_in(l);
+    }
     PostParams q{};
     q.N = N; q.nel = nel; q.E = E; q.nasa_t = pin.nasa_t; q.invW = pin.invW;
     q.norm = P + weights_count(); q.tau_T = pin.tau_T; q.y_min = pin.y_min; q.margin = pin.margin;
@@ -807,9 +938,12 @@ int Surrogate::apply(const FeatSrc &f, double *T, double *Y, uint8_t *flags, con
     TgtSrc t{};
     for (int64_t base = 0; base < n; base += chunk) {
         const int m = (int)std::min<int64_t>(chunk, n - base);
-        hipLaunchKernelGGL(k_build_rows, dim3((m + 3) / 4), dim3(256), 0, s, f, t, (const int *)nullptr,
-                           base, m, P + weights_count(), X, (uint16_t *)nullptr, 0, (float *)nullptr);
-        forward(m, false, true, s);
+        // only offered rows go through the network (fused, one kernel)
+        hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, sel_cnt);
+        hipLaunchKernelGGL(k_sur_select, dim3((m + 255) / 256), dim3(256), 0, s, flags, T, base, m,
+                           pin.T_max, idx, sel_cnt);
+        hipLaunchKernelGGL(k_mlp_infer, dim3((m + FT - 1) / FT), dim3(256), kInferLds, s, f, base, m,
+                           idx, sel_cnt, P + weights_count(), wts, out);
         launch_post(nel, dim3((m + 255) / 256), s, f, base, m, out, q, T, Y, flags, stats);
     }
     SCHK(hipGetLastError());

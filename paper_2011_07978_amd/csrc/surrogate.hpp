@@ -56,6 +56,7 @@ struct Surrogate {
     uint16_t *dZ5 = nullptr, *dZ5T = nullptr, *dZb = nullptr, *dZbT = nullptr;
     float *csum = nullptr;   // partial column sums of the bias gradients
     int *idx = nullptr;
+    int *sel_cnt = nullptr;  // rows selected for inference
 
     ~Surrogate();
     int init(int N, int nel, const std::vector<double> &E_host, char *err);
