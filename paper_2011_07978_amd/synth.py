@@ -254,6 +254,10 @@ MECH_SPECS = {
     "small": dict(n_species=10, n_reactions=20, n_elements=3, seed=1, third_body_frac=0.0),
     "mech53": dict(n_species=53, n_reactions=325, n_elements=4, seed=2, third_body_frac=0.2),
     "mech130": dict(n_species=130, n_reactions=1000, n_elements=4, seed=3, third_body_frac=0.2),
+    # the two sides of the boundary between the one-wavefront integrator
+    # (n = N + 1 <= 64) and the workgroup integrator
+    "mech63": dict(n_species=63, n_reactions=400, n_elements=4, seed=4, third_body_frac=0.2),
+    "mech64": dict(n_species=64, n_reactions=400, n_elements=4, seed=5, third_body_frac=0.2),
 }
 
 _MECH_CACHE = {}
