@@ -366,6 +366,43 @@ int chem_eval_rhs_jac(chem_ctx *ctx, int64_t n_cells, const double *T, const dou
 int chem_rodas_step(chem_ctx *ctx, int64_t n_cells, const double *T, const double *p,
                     const double *Y, double h, double *ynew, double *err);
 
+/* ---------------------------------------------------------------------------
+ * Load-balancing plan across processes (Algorithm 1, Sec. 2.2).  Host only:
+ * no device, context or mechanism needed.  On one GPU the work queue does the
+ * balancing; this plan is what the paper's processes (or several GPUs,
+ * sharding cells by cost) would exchange.
+ *
+ * n_proc processes; process k holds n_prob[k] problems whose costs (e.g. CPU
+ * time or attempted steps of the previous step) are t_cost[off_k ..
+ * off_k + n_prob[k]), off_k = n_prob[0] + ... + n_prob[k-1], in its own list
+ * order.  The plan:
+ *   - loads l_k = sum of the process's costs (in list order), mean L = sum l / n_proc;
+ *   - loads sorted ascending (ties by process index), receiver pointer i at the
+ *     lightest, sender pointer j at the heaviest;
+ *   - while i != j: dL = min(L - L_i, L_j - L); the sender's next problems, in
+ *     its list order from where its last emitted send stopped, up to the first
+ *     prefix whose cost reaches dL (all that remain if none does), make one
+ *     operation (sender, receiver, count); L_i += dL, L_j -= dL; i advances if
+ *     |L_i - L| <= 1e-12 L, else j retreats;
+ *   - an operation with dL < min_frac * L (the paper uses 0.01) is computed but
+ *     not emitted (no problems move).
+ * ops (host) receives up to max_ops operations in the order found (n_ops: how
+ * many were emitted, possibly more than max_ops, in which case
+ * CHEM_E_INVALID_ARG is returned after filling max_ops); loads_after (host,
+ * nullable, n_proc) the loads once the emitted operations move their
+ * problems.  Errors: n_proc < 1, negative counts, non-finite or negative
+ * costs, null arrays (CHEM_E_INVALID_ARG). */
+typedef struct {
+    int32_t sender, receiver;
+    int64_t first;     /* index in the sender's list of the first problem sent */
+    int64_t count;     /* problems sent: first .. first + count - 1 */
+    double load;       /* their summed cost */
+    double planned;    /* dL of the algorithm for this pair */
+} chem_balance_op;
+
+int chem_plan_balance(int32_t n_proc, const int64_t *n_prob, const double *t_cost, double min_frac,
+                      chem_balance_op *ops, int64_t max_ops, int64_t *n_ops, double *loads_after);
+
 #ifdef __cplusplus
 }
 #endif

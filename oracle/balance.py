@@ -53,3 +53,57 @@ def slot_loads(config: str, n_slots: int, n_per_slot: int, xi: float) -> np.ndar
 def ideal_speedup(loads: np.ndarray) -> float:
     """Static time (slowest process) over perfectly balanced time (mean load)."""
     return float(np.max(loads) / np.mean(loads))
+
+
+def plan_balance(n_prob, t_cost, min_frac=0.01):
+    """Algorithm 1 (Sec. 2.2), plain loops: the list of balancing operations
+    (sender, receiver, first, count, load, planned) and the loads after they
+    move their problems.
+
+    Readings of the garbled passages: the mean load is the sum of the loads
+    over the number of processes; "|L_i - mean| ~ 0" is |L_i - mean| <= 1e-12
+    mean; "find N_send s.t. dL ~ sum t" takes, in the sender's list order
+    from where its last emitted send stopped, the shortest prefix whose cost
+    reaches dL (all remaining problems if none does); operations with
+    dL < min_frac * mean are computed but not emitted."""
+    n_prob = [int(v) for v in n_prob]
+    n_proc = len(n_prob)
+    lists, pos = [], 0
+    for k in range(n_proc):
+        lists.append([float(t) for t in t_cost[pos:pos + n_prob[k]]])
+        pos += n_prob[k]
+    loads = []
+    for k in range(n_proc):
+        s = 0.0
+        for t in lists[k]:
+            s += t
+        loads.append(s)
+    total = 0.0
+    for v in loads:
+        total += v
+    mean = total / n_proc
+    order = sorted(range(n_proc), key=lambda k: (loads[k], k))
+    L = [loads[k] for k in order]
+    after = list(loads)
+    cursor = [0] * n_proc
+    ops = []
+    i, j = 0, n_proc - 1
+    while i != j:
+        dL = min(mean - L[i], L[j] - mean)
+        rr, rs = order[i], order[j]
+        first, cnt, sent = cursor[rs], 0, 0.0
+        while first + cnt < n_prob[rs] and sent < dL:
+            sent += lists[rs][first + cnt]
+            cnt += 1
+        if dL >= min_frac * mean and cnt > 0:
+            ops.append((rs, rr, first, cnt, sent, dL))
+            cursor[rs] += cnt
+            after[rs] -= sent
+            after[rr] += sent
+        L[i] += dL
+        L[j] -= dL
+        if abs(L[i] - mean) <= 1e-12 * mean:
+            i += 1
+        else:
+            j -= 1
+    return ops, np.array(after)

@@ -10,7 +10,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libchem.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.cpp", "integrate.hip", "integrate_big.hip", "map_queue.hip", "mlp.hip"]
+SOURCES = ["api.cpp", "balance.cpp", "integrate.hip", "integrate_big.hip", "map_queue.hip", "mlp.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
           # packed FP32 instructions are kept out of every kernel

@@ -38,6 +38,34 @@ class Options(C.Structure):
                 ("slots_per_cu", C.c_int32), ("order_by_cost", C.c_int32)]
 
 
+class BalanceOp(C.Structure):
+    _fields_ = [("sender", C.c_int32), ("receiver", C.c_int32), ("first", C.c_int64),
+                ("count", C.c_int64), ("load", C.c_double), ("planned", C.c_double)]
+
+
+def plan_balance(n_prob, t_cost, min_frac=0.01):
+    """Algorithm 1 (Sec. 2.2) on the host: returns (operations, loads_after).
+    operations: list of (sender, receiver, first, count, load, planned);
+    n_prob[k] problems per process, t_cost their costs concatenated in list
+    order.  Needs no GPU."""
+    import numpy as np
+    L = load_library()
+    n_prob = np.ascontiguousarray(n_prob, dtype=np.int64)
+    t_cost = np.ascontiguousarray(t_cost, dtype=np.float64)
+    n_proc = int(n_prob.size)
+    max_ops = max(1, 2 * n_proc)
+    ops = (BalanceOp * max_ops)()
+    n_ops = C.c_int64(0)
+    after = np.zeros(max(n_proc, 1), dtype=np.float64)
+    rc = L.chem_plan_balance(n_proc, n_prob.ctypes.data_as(C.POINTER(C.c_int64)),
+                             t_cost.ctypes.data_as(C.POINTER(C.c_double)), float(min_frac), ops,
+                             max_ops, C.byref(n_ops), after.ctypes.data_as(C.POINTER(C.c_double)))
+    if rc != 0:
+        raise ChemError(f"chem_plan_balance failed ({rc})")
+    out = [(o.sender, o.receiver, o.first, o.count, o.load, o.planned) for o in ops[:n_ops.value]]
+    return out, after[:n_proc]
+
+
 class MapParams(C.Structure):
     _fields_ = [("Z_tol", C.c_double), ("T_tol", C.c_double), ("use_T", C.c_int32),
                 ("Y_fuel", _d), ("Y_ox", _d)]
@@ -72,7 +100,7 @@ class TuneEntry(C.Structure):
 
 EXPORTS = ["chem_create", "chem_destroy", "chem_set_stream", "chem_last_error",
            "chem_set_mechanism", "chem_max_species", "chem_set_options", "chem_get_options",
-           "chem_query_slots",
+           "chem_query_slots", "chem_plan_balance",
            "chem_default_options", "chem_reserve", "chem_map_reference", "chem_integrate",
            "chem_eval_rhs_jac", "chem_rodas_step", "chem_integrate_surrogate",
            "chem_default_train_params", "chem_default_gate_params", "chem_surrogate_param_count",
@@ -106,6 +134,9 @@ def load_library(path: str = LIB_PATH):
     L.chem_set_options.argtypes = [vp, C.POINTER(Options)]
     L.chem_get_options.argtypes = [vp, C.POINTER(Options)]
     L.chem_query_slots.argtypes = [vp, C.POINTER(C.c_int64)]
+    L.chem_plan_balance.argtypes = [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                    C.c_double, C.POINTER(BalanceOp), C.c_int64,
+                                    C.POINTER(C.c_int64), C.POINTER(C.c_double)]
     L.chem_default_options.argtypes = [C.POINTER(Options)]
     L.chem_default_options.restype = None
     L.chem_reserve.argtypes = [vp, C.c_int64]

@@ -95,6 +95,15 @@ def unit_benchmark(chem, torch, synth, mech, n_per_slot=100, reps=3,
         call(CHEM_SCHED_QUEUE, True)          # first call: per-cell cost for the next ones
         c = cost.cpu().numpy().astype(np.float64)
         xi = float(c[is_heavy].mean() / max(c[~is_heavy].mean(), 1e-30))
+        # what the paper's planner (Algorithm 1) would move between the slots,
+        # on the same per-cell costs: slowest slot before and after
+        from paper_2011_07978_amd.chem import plan_balance
+        ops, after = plan_balance(np.full(slots, n_per_slot), c, 0.01)
+        before = c.reshape(slots, n_per_slot).sum(axis=1)
+        alg1 = {"operations": len(ops), "problems_moved": int(sum(o[3] for o in ops)),
+                "max_load_before": float(before.max()), "max_load_after": float(after.max()),
+                "mean_load": float(before.mean()),
+                "chi_planned": float(before.max() / after.max())}
         t_bal = _median_ms(lambda: call(CHEM_SCHED_QUEUE, True)["ms_total"], reps)
         t_unb = _median_ms(lambda: call(CHEM_SCHED_BLOCKS, False)["ms_total"], reps)
         t_plain = _median_ms(lambda: call(CHEM_SCHED_PLAIN, False)["ms_total"], reps)
@@ -104,11 +113,13 @@ def unit_benchmark(chem, torch, synth, mech, n_per_slot=100, reps=3,
              "ms_plain_one_cell_per_workgroup": t_plain,
              "chi_su": t_unb / t_bal, "chi_su_bound": speedup_bound(theta, x, xi),
              "chi_su_bound_time": speedup_bound(theta, x, xi_time),
-             "chi_plain_over_queue": t_plain / t_bal}
+             "chi_plain_over_queue": t_plain / t_bal, "algorithm1_plan": alg1}
         out["layouts"][name] = r
         log(f"unit {name}: x {x} theta {theta} xi {xi:.1f}: blocks {t_unb:.1f} ms, queue {t_bal:.1f} ms, "
             f"plain {t_plain:.1f} ms -> chi_su {r['chi_su']:.2f} (bound {r['chi_su_bound']:.2f} "
-            f"from attempts, {r['chi_su_bound_time']:.2f} from time)")
+            f"from attempts, {r['chi_su_bound_time']:.2f} from time); Algorithm 1 plan: "
+            f"{alg1['operations']} operations, {alg1['problems_moved']} problems, "
+            f"planned chi {alg1['chi_planned']:.2f}")
     return out
 
 

@@ -56,3 +56,88 @@ def test_product_bound_matches_oracle():
         x, theta, xi = rng.uniform(0.05, 1.0), rng.uniform(0.05, 1.0), 10 ** rng.uniform(0, 4)
         assert studies.speedup_bound(theta, x, xi) == pytest.approx(
             balance.speedup_bound(theta, x, xi), rel=1e-13)
+
+
+# ---------------------------------------------------------------- Algorithm 1
+def test_plan_hand_worked_one_heavy_process():
+    """Loads 1, 1, 1, 5 of unit problems, mean 2: the heavy process sends one
+    problem to each light one, in its list order."""
+    ops, after = balance.plan_balance([1, 1, 1, 5], [1.0] * 8)
+    assert [(o[0], o[1], o[2], o[3]) for o in ops] == [(3, 0, 0, 1), (3, 1, 1, 1), (3, 2, 2, 1)]
+    assert list(after) == [2.0, 2.0, 2.0, 2.0]
+
+
+def test_plan_hand_worked_two_senders():
+    """Loads 0, 0, 6, 6 (three problems of cost 2 each on the heavy ones),
+    mean 3: process 3 sends to 0, then 2 to 0 ... worked by hand."""
+    ops, after = balance.plan_balance([0, 0, 3, 3], [2.0] * 6)
+    # sorted: (0:0), (1:0), (2:6), (3:6); i=0 (proc 0), j=3 (proc 3)
+    # dL = min(3, 3) = 3 -> proc 3 sends 2 problems (4 >= 3) to proc 0; L0 = 3 -> i = 1
+    # dL = min(3, 0) = 0 -> below threshold, nothing moves; L3 = 3 -> j = 2
+    # dL = min(3, 3) = 3 -> proc 2 sends 2 problems to proc 1; i = 2 = j
+    assert [(o[0], o[1], o[2], o[3]) for o in ops] == [(3, 0, 0, 2), (2, 1, 0, 2)]
+    assert list(after) == [4.0, 4.0, 2.0, 2.0]
+
+
+def test_plan_balanced_input_moves_nothing():
+    ops, after = balance.plan_balance([4, 4, 4], [1.0] * 12)
+    assert ops == [] and list(after) == [4.0, 4.0, 4.0]
+
+
+def test_plan_small_imbalance_is_not_emitted():
+    """dL below 1 % of the mean load is planned but not sent."""
+    ops, _ = balance.plan_balance([100, 100], [1.0] * 100 + [1.0] * 99 + [1.5])
+    assert ops == []
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_plan_properties_random(seed):
+    rng = np.random.default_rng(seed)
+    n_proc = int(rng.integers(2, 40))
+    n_prob = rng.integers(0, 60, n_proc)
+    t = rng.lognormal(0.0, 1.0, int(n_prob.sum())) * np.repeat(rng.uniform(0.2, 5.0, n_proc), n_prob)
+    ops, after = balance.plan_balance(n_prob, t)
+    loads = np.array([t[a:b].sum() for a, b in zip(np.r_[0, np.cumsum(n_prob)[:-1]], np.cumsum(n_prob))])
+    assert after.sum() == pytest.approx(loads.sum(), rel=1e-12)
+    # every problem leaves its process at most once, in list order
+    sent = {}
+    for s_, r_, first, cnt, load, planned in ops:
+        assert s_ != r_ and cnt > 0
+        assert first == sent.get(s_, 0)
+        sent[s_] = first + cnt
+        assert first + cnt <= n_prob[s_]
+        offs = int(np.r_[0, np.cumsum(n_prob)][s_])
+        assert load == pytest.approx(t[offs + first: offs + first + cnt].sum(), rel=1e-12)
+        # shortest prefix: dropping the last problem would fall short
+        assert load - t[offs + first + cnt - 1] < planned or first + cnt == n_prob[s_]
+    # no process sends and receives
+    senders = {o[0] for o in ops}
+    receivers = {o[1] for o in ops}
+    assert not senders & receivers
+    # each send overshoots its planned load by less than one problem, so a
+    # receiver ends within (sends received) problems above the mean
+    mean = loads.mean()
+    for r_ in receivers:
+        k = sum(1 for o in ops if o[1] == r_)
+        assert after[r_] <= mean + k * t.max() + 1e-9 * mean
+    for o in ops:
+        assert o[4] - o[5] < t.max() or o[3] == 1
+
+
+def test_library_plan_matches_oracle():
+    """The library's planner (host C++) against this one, operation by
+    operation and bit for bit (no GPU needed)."""
+    from paper_2011_07978_amd import chem
+    try:
+        chem.load_library()
+    except RuntimeError:
+        pytest.skip("libchem.so not built")
+    for seed in range(20):
+        rng = np.random.default_rng(100 + seed)
+        n_proc = int(rng.integers(1, 64))
+        n_prob = rng.integers(0, 80, n_proc)
+        t = rng.exponential(1.0, int(n_prob.sum())) * np.repeat(rng.uniform(0.1, 10.0, n_proc), n_prob)
+        ops_o, after_o = balance.plan_balance(n_prob, t)
+        ops_l, after_l = chem.plan_balance(n_prob, t)
+        assert ops_l == ops_o, seed
+        assert np.array_equal(after_l, after_o), seed
