@@ -79,16 +79,21 @@ class Oracle:
         self.N = int(mech.n_species)
         self.n = self.N + 1
         self.R = int(mech.n_reactions)
+        fo_t = getattr(mech, "falloff", None)
+        fo_p = getattr(mech, "fo_params", None)
+        if fo_t is None:
+            fo_t, fo_p = np.zeros(self.R, np.int32), np.zeros((self.R, 7))
         self._keep = [_f64(mech.elem_mass), _i(mech.composition), _f64(mech.W), _f64(mech.nasa),
                       _i(mech.reactants), _i(mech.products), _f64(mech.A), _f64(mech.b),
                       _f64(mech.Ea), _i(mech.third_body), _i(mech.eff_reaction),
-                      _i(mech.eff_species), _f64(mech.eff_value)]
+                      _i(mech.eff_species), _f64(mech.eff_value), _i(fo_t), _f64(fo_p)]
         k = self._keep
         h = C.c_void_p()
         rc = L.orc_mech_create(C.byref(h), int(mech.n_elements), self.N, self.R,
                                _p(k[0]), _p(k[1], _i32), _p(k[2]), _p(k[3]), _p(k[4], _i32),
                                _p(k[5], _i32), _p(k[6]), _p(k[7]), _p(k[8]), _p(k[9], _i32),
-                               int(len(k[12])), _p(k[10], _i32), _p(k[11], _i32), _p(k[12]))
+                               int(len(k[12])), _p(k[10], _i32), _p(k[11], _i32), _p(k[12]),
+                               _p(k[13], _i32), _p(k[14]))
         if rc != 0:
             raise RuntimeError("orc_mech_create failed")
         self.h = h
@@ -104,6 +109,13 @@ class Oracle:
         cp, h, s = (np.zeros(self.N) for _ in range(3))
         lib().orc_thermo(self.h, C.c_double(T), _p(cp), _p(h), _p(s))
         return cp, h, s
+
+    def falloff_factor(self, j, T, M):
+        """G of reaction j (its rate constant is k_inf G); [M] itself when j has
+        no fall-off form."""
+        f = lib().orc_falloff_factor
+        f.restype = C.c_double
+        return f(self.h, C.c_int(int(j)), C.c_double(T), C.c_double(M))
 
     def kinetics(self, T, p, Y):
         Y = _f64(Y)

@@ -11,21 +11,33 @@
 #define SC_EXP exp
 #define SC_LOG log
 #define FN_RHS rhs_real
+#define FN_FALLOFF falloff_real
 #include "rhs_body.h"
 #undef SC
 #undef SC_EXP
 #undef SC_LOG
 #undef FN_RHS
+#undef FN_FALLOFF
 
 #define SC double complex
 #define SC_EXP cexp
 #define SC_LOG clog
 #define FN_RHS rhs_cplx
+#define FN_FALLOFF falloff_cplx
 #include "rhs_body.h"
 #undef SC
 #undef SC_EXP
 #undef SC_LOG
 #undef FN_RHS
+#undef FN_FALLOFF
+
+double orc_falloff_factor(const omech *m, int j, double T, double M)
+{
+    if (!m->fo_type[j]) return M;
+    const double lnT = log(T);
+    const double kinf = exp(m->lnA[j] + m->b[j] * lnT - m->Ea[j] / (ORC_RU_J * T));
+    return falloff_real(m, j, T, lnT, kinf, M);
+}
 
 void orc_rhs(const omech *m, double p, const double *y, double *f)
 {
@@ -125,6 +137,7 @@ void orc_kinetics(const omech *m, double T, double p, const double *Y,
             mj = 0.0;
             for (int k = 0; k < N; ++k) mj += m->alpha[(size_t)j * N + k] * C[k];
         }
+        if (m->fo_type[j]) mj = falloff_real(m, j, T, lnT, kf[j], mj);
         q[j] = mj * (kf[j] * Pf - kr[j] * Pr);
         for (int s2 = 0; s2 < 2; ++s2) if (rs[s2] >= 0) omega[rs[s2]] -= q[j];
         for (int s3 = 0; s3 < 3; ++s3) if (ps[s3] >= 0) omega[ps[s3]] += q[j];
@@ -138,6 +151,10 @@ void orc_kinetics(const omech *m, double T, double p, const double *Y,
  * JCT = d omega / dT at fixed C, then the transformation to (T, Y). */
 void orc_jac(const omech *m, double p, const double *y, double *J)
 {
+    if (m->has_falloff) {
+        orc_jac_cs(m, p, y, J);
+        return;
+    }
     const int N = m->N, R = m->R, n = N + 1;
     const double T = y[0];
     const double *Y = y + 1;

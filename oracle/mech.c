@@ -9,7 +9,8 @@ int orc_mech_create(omech **out, int E, int N, int R,
                     const double *nasa, const int32_t *reac, const int32_t *prod,
                     const double *A, const double *b, const double *Ea,
                     const int32_t *tb, int n_eff, const int32_t *eff_r,
-                    const int32_t *eff_s, const double *eff_v)
+                    const int32_t *eff_s, const double *eff_v,
+                    const int32_t *fo_type, const double *fo_params)
 {
     omech *m = (omech *)calloc(1, sizeof(omech));
     if (!m) return -1;
@@ -26,6 +27,9 @@ int orc_mech_create(omech **out, int E, int N, int R,
     m->tb = (int *)malloc(sizeof(int) * R);
     m->alpha = (double *)malloc(sizeof(double) * R * N);
     m->sum_nu = (int *)malloc(sizeof(int) * R);
+    m->fo_type = (int *)calloc((size_t)R, sizeof(int));
+    m->fo = (double *)calloc((size_t)R * 7, sizeof(double));
+    m->has_falloff = 0;
     for (int e = 0; e < E; ++e) m->elem_mass[e] = elem_mass[e];
     for (int i = 0; i < N * E; ++i) m->comp[i] = comp[i];
     for (int k = 0; k < N; ++k) m->W[k] = W[k];
@@ -43,6 +47,12 @@ int orc_mech_create(omech **out, int E, int N, int R,
     }
     for (int i = 0; i < n_eff; ++i)
         m->alpha[(size_t)eff_r[i] * N + eff_s[i]] = eff_v[i];
+    if (fo_type && fo_params)
+        for (int j = 0; j < R; ++j) {
+            m->fo_type[j] = fo_type[j];
+            for (int c = 0; c < 7; ++c) m->fo[(size_t)j * 7 + c] = fo_params[(size_t)j * 7 + c];
+            if (fo_type[j]) m->has_falloff = 1;
+        }
     *out = m;
     return 0;
 }
@@ -52,6 +62,6 @@ void orc_mech_destroy(omech *m)
     if (!m) return;
     free(m->elem_mass); free(m->comp); free(m->W); free(m->nasa);
     free(m->reac); free(m->prod); free(m->lnA); free(m->b); free(m->Ea);
-    free(m->tb); free(m->alpha); free(m->sum_nu);
+    free(m->tb); free(m->alpha); free(m->sum_nu); free(m->fo_type); free(m->fo);
     free(m);
 }

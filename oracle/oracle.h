@@ -48,6 +48,9 @@ typedef struct omech {
     int    *tb;          /* [R] third-body flag */
     double *alpha;       /* [R*N] third-body efficiencies (1 unless listed) */
     int    *sum_nu;      /* [R] (#product slots) - (#reactant slots) */
+    int    *fo_type;     /* [R] fall-off form: 0 none, 1 Lindemann, 2 Troe */
+    double *fo;          /* [R*7] A0, b0, Ea0 (J/mol), a, T3, T1, T2 (T2 <= 0: no T2 term) */
+    int    has_falloff;
 } omech;
 
 typedef struct {
@@ -68,8 +71,11 @@ int  orc_mech_create(omech **out, int E, int N, int R,
                      const double *nasa, const int32_t *reac, const int32_t *prod,
                      const double *A, const double *b, const double *Ea,
                      const int32_t *tb, int n_eff, const int32_t *eff_r,
-                     const int32_t *eff_s, const double *eff_v);
+                     const int32_t *eff_s, const double *eff_v,
+                     const int32_t *fo_type, const double *fo_params);
 void orc_mech_destroy(omech *m);
+/* fall-off factor G(T, [M]) of reaction j: its rate constant is k_inf G */
+double orc_falloff_factor(const omech *m, int j, double T, double M);
 
 /* thermo (per species, nondimensional) */
 void orc_thermo(const omech *m, double T, double *cp_R, double *h_RT, double *s_R);
@@ -80,7 +86,8 @@ void orc_kinetics(const omech *m, double T, double p, const double *Y,
 
 /* right-hand side f(y), y = (T, Y_1..Y_N) */
 void orc_rhs(const omech *m, double p, const double *y, double *f);
-/* analytic Jacobian, row-major n x n, J[i*n + j] = d f_i / d y_j */
+/* analytic Jacobian, row-major n x n, J[i*n + j] = d f_i / d y_j (for
+ * mechanisms with fall-off reactions: the complex-step Jacobian) */
 void orc_jac(const omech *m, double p, const double *y, double *J);
 /* complex-step Jacobian (step 1e-30 i), same layout */
 void orc_jac_cs(const omech *m, double p, const double *y, double *J);

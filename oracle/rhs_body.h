@@ -2,7 +2,7 @@
  *
  * Included twice by chem.c: once with SC = double and once with
  * SC = double complex (for the complex-step Jacobian), so both evaluate the
- * same formulas.  Required macros: SC, SC_EXP, SC_LOG, FN_RHS.
+ * same formulas.  Required macros: SC, SC_EXP, SC_LOG, FN_RHS, FN_FALLOFF.
  *
  * State y = (T, Y_1..Y_N) at fixed pressure p.  With W-bar the mean molar
  * mass, rho = p W-bar / (R T) and C_k = rho Y_k / W_k:
@@ -10,7 +10,17 @@
  *   ln Kc  = -sum_k nu_kj G_k/(RT) + (sum_k nu_kj) ln(p_atm / (R T))
  *   k_r,j  = exp(ln k_f,j - ln Kc,j)
  *   q_j    = m_j (k_f prod_reactants C - k_r prod_products C),
- *            m_j = sum_k alpha_kj C_k for third-body reactions, else 1
+ *            m_j = [M]_j = sum_k alpha_kj C_k for third-body reactions, else 1;
+ *            for fall-off reactions m_j = G([M]_j, T) instead (FN_FALLOFF):
+ *            k_f is the high-pressure limit k_inf, and
+ *              Pr = k0 [M] / k_inf,  k0 = A0 T^b0 exp(-Ea0 / (R T)),
+ *              G  = Pr / (1 + Pr) F,
+ *            F = 1 (Lindemann) or Troe's broadening factor:
+ *              Fcent = (1 - a) exp(-T/T3) + a exp(-T/T1) + exp(-T2/T)  (last if T2 > 0)
+ *              c = -0.4 - 0.67 log10 Fcent,  n = 0.75 - 1.27 log10 Fcent,  d = 0.14
+ *              f1 = (log10 Pr + c) / (n - d (log10 Pr + c))
+ *              log10 F = log10 Fcent / (1 + f1^2)
+ *            (the reverse rate k_f / Kc carries the same factor)
  *   omega_k = sum_j nu_kj q_j
  *   dY_k/dt = W_k omega_k / rho
  *   dT/dt   = -sum_k H_k omega_k / (rho cp)      (cp mass specific)
@@ -19,6 +29,25 @@
  *   H/RT = a1 + a2 T/2 + a3 T^2/3 + a4 T^3/4 + a5 T^4/5 + a6/T
  *   S/R  = a1 ln T + a2 T + a3 T^2/2 + a4 T^3/3 + a5 T^4/4 + a7
  */
+
+static SC FN_FALLOFF(const omech *m, int j, SC T, SC lnT, SC kinf, SC M)
+{
+    const double *fp = m->fo + (size_t)7 * j;
+    const SC k0 = SC_EXP(log(fp[0]) + fp[1] * lnT - fp[2] / (ORC_RU_J * T));
+    const SC Pr = k0 * M / kinf;
+    SC G = Pr / (1.0 + Pr);
+    if (m->fo_type[j] == 2) {
+        SC Fc = (1.0 - fp[3]) * SC_EXP(-T / fp[4]) + fp[3] * SC_EXP(-T / fp[5]);
+        if (fp[6] > 0.0) Fc += SC_EXP(-fp[6] / T);
+        const double ln10 = log(10.0);
+        const SC lFc = SC_LOG(Fc) / ln10;
+        const SC c = -0.4 - 0.67 * lFc, nn = 0.75 - 1.27 * lFc;
+        const SC x = SC_LOG(Pr) / ln10 + c;
+        const SC f1 = x / (nn - 0.14 * x);
+        G *= SC_EXP(ln10 * lFc / (1.0 + f1 * f1));
+    }
+    return G;
+}
 
 static void FN_RHS(const omech *m, double p, const SC *y, SC *f)
 {
@@ -65,6 +94,7 @@ static void FN_RHS(const omech *m, double p, const SC *y, SC *f)
             mj = 0.0;
             for (int k = 0; k < N; ++k) mj += m->alpha[(size_t)j * N + k] * C[k];
         }
+        if (m->fo_type[j]) mj = FN_FALLOFF(m, j, T, lnT, kf, mj);
         SC q = mj * (kf * Pf - kr * Pr);
         for (int s = 0; s < 2; ++s) if (rs[s] >= 0) omega[rs[s]] -= q;
         for (int s = 0; s < 3; ++s) if (ps[s] >= 0) omega[ps[s]] += q;

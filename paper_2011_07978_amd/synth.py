@@ -55,11 +55,15 @@ class Mechanism:
     eff_value: np.ndarray          # [n_eff] float64
     seed: int = 0
     name: str = ""
+    falloff: np.ndarray = None     # [R] int32 0 none, 1 Lindemann, 2 Troe (third-body reactions)
+    fo_params: np.ndarray = None   # [R, 7] A0 (CGS), b0, Ea0 (J/mol), a, T3, T1, T2 (<= 0: absent)
 
     def arrays(self):
-        return {k: getattr(self, k) for k in (
-            "elem_mass", "composition", "W", "nasa", "reactants", "products",
-            "A", "b", "Ea", "third_body", "eff_reaction", "eff_species", "eff_value")}
+        keys = ["elem_mass", "composition", "W", "nasa", "reactants", "products",
+                "A", "b", "Ea", "third_body", "eff_reaction", "eff_species", "eff_value"]
+        if self.falloff is not None:
+            keys += ["falloff", "fo_params"]
+        return {k: getattr(self, k) for k in keys}
 
     def save(self, path):
         np.savez(path, n_elements=self.n_elements, n_species=self.n_species,
@@ -165,7 +169,8 @@ def _balanced_pairs(comp, inert):
 
 
 def make_mechanism(n_species: int, n_reactions: int, n_elements: int, seed: int,
-                   third_body_frac: float = 0.2, name: str = "") -> Mechanism:
+                   third_body_frac: float = 0.2, name: str = "",
+                   falloff_frac: float = 0.0) -> Mechanism:
     """Seeded synthetic reversible mechanism (see module docstring).
 
     Thermo: a1 ~ U(2.5, 4.5) + (atoms - 1)/2; a2..a5 = u a1 / (8 T_MAX^(m-1)),
@@ -179,6 +184,13 @@ def make_mechanism(n_species: int, n_reactions: int, n_elements: int, seed: int,
     Ea ~ U(0, 200) kJ/mol.  Third-body reactions are association/dissociation
     pairs; up to three species per third-body reaction get an efficiency
     ~ U(0.5, 5), all others 1.
+    Fall-off (falloff_frac of the third-body reactions, half Lindemann, half
+    Troe): the reaction's Arrhenius form is the high-pressure limit, the
+    low-pressure limit has A0 = A 10^U(4, 8) cm^3/mol (so Pr = k0 [M] / k_inf
+    spans the fall-off region at 1 atm), b0 ~ U(-2, 0), Ea0 = Ea U(0.5, 1);
+    Troe a ~ U(0.2, 0.9), T3 = 10^U(1.5, 3) K, T1 = 10^U(3, 4) K and, for half
+    of them, T2 = 10^U(3, 4) K (else absent).  These draws come after all
+    others, so a mechanism without fall-off is unchanged by the option.
     """
     rng = _rng(seed)
     T_MAX = 10000.0
@@ -241,10 +253,29 @@ def make_mechanism(n_species: int, n_reactions: int, n_elements: int, seed: int,
     A = 10.0 ** rng.uniform(6.0, 14.0, size=R)
     b = rng.uniform(-1.0, 1.0, size=R)
     Ea = rng.uniform(0.0, 200.0e3, size=R)
+    falloff = fo_params = None
+    if falloff_frac > 0.0:
+        tbj = np.nonzero(third)[0]
+        n_fo = int(round(falloff_frac * tbj.size))
+        pick = np.sort(rng.choice(tbj, size=n_fo, replace=False))
+        falloff = np.zeros(R, dtype=np.int32)
+        fo_params = np.zeros((R, 7))
+        for q, j in enumerate(pick):
+            troe = q % 2 == 1
+            falloff[j] = 2 if troe else 1
+            fo_params[j, 0] = A[j] * 10.0 ** rng.uniform(4.0, 8.0)
+            fo_params[j, 1] = rng.uniform(-2.0, 0.0)
+            fo_params[j, 2] = Ea[j] * rng.uniform(0.5, 1.0)
+            if troe:
+                fo_params[j, 3] = rng.uniform(0.2, 0.9)
+                fo_params[j, 4] = 10.0 ** rng.uniform(1.5, 3.0)
+                fo_params[j, 5] = 10.0 ** rng.uniform(3.0, 4.0)
+                fo_params[j, 6] = 10.0 ** rng.uniform(3.0, 4.0) if rng.uniform() < 0.5 else 0.0
     return Mechanism(n_elements, n_species, R, elem_mass, comp, W, nasa,
                      reactants, products, A, b, Ea, third,
                      np.array(eff_r, dtype=np.int32), np.array(eff_s, dtype=np.int32),
-                     np.array(eff_v, dtype=np.float64), seed=seed, name=name)
+                     np.array(eff_v, dtype=np.float64), seed=seed, name=name,
+                     falloff=falloff, fo_params=fo_params)
 
 
 # ----------------------------------------------------------------------------
@@ -258,6 +289,11 @@ MECH_SPECS = {
     # (n = N + 1 <= 64) and the workgroup integrator
     "mech63": dict(n_species=63, n_reactions=400, n_elements=4, seed=4, third_body_frac=0.2),
     "mech64": dict(n_species=64, n_reactions=400, n_elements=4, seed=5, third_body_frac=0.2),
+    # fall-off kinetics (Lindemann and Troe) on half of the third-body reactions
+    "mech53fo": dict(n_species=53, n_reactions=325, n_elements=4, seed=6, third_body_frac=0.2,
+                     falloff_frac=0.5),
+    "mech64fo": dict(n_species=64, n_reactions=400, n_elements=4, seed=7, third_body_frac=0.2,
+                     falloff_frac=0.5),
 }
 
 _MECH_CACHE = {}
