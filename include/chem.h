@@ -82,7 +82,16 @@ typedef struct chem_ctx chem_ctx;
  * product slots (-1 = unused slot; a species may fill two slots); reverse rate
  * constants follow from equilibrium constants of the NASA-7 style single-range
  * thermodynamics.  Third-body reactions multiply the rate by
- * [M] = sum_k alpha_k C_k with alpha_k = 1 unless listed in eff_*. */
+ * [M] = sum_k alpha_k C_k with alpha_k = 1 unless listed in eff_*.
+ * Fall-off reactions (third-body reactions with falloff[j] = 1 Lindemann or
+ * 2 Troe) use instead the rate constant k_inf G: A, b, Ea give the
+ * high-pressure limit k_inf, falloff_params[7j..7j+6] = A0, b0, Ea0 (J/mol)
+ * the low-pressure limit k0, then Troe's a, T3, T1, T2 (K; T2 <= 0: no T2
+ * term), and with Pr = k0 [M] / k_inf, G = Pr / (1 + Pr) F, F = 1 (Lindemann)
+ * or log10 F = log10 Fcent / (1 + f1^2), f1 = x / (n - 0.14 x),
+ * x = log10 Pr - 0.4 - 0.67 log10 Fcent, n = 0.75 - 1.27 log10 Fcent,
+ * Fcent = (1 - a) exp(-T/T3) + a exp(-T/T1) + exp(-T2/T) (Troe).  The
+ * reverse rate carries the same G. */
 typedef struct {
     int32_t n_elements, n_species, n_reactions;
     const double *elem_mass;     /* [E] g/mol */
@@ -100,6 +109,8 @@ typedef struct {
     const int32_t *eff_reaction; /* [n_eff] reaction index (must be third-body) */
     const int32_t *eff_species;  /* [n_eff] species index */
     const double *eff_value;     /* [n_eff] efficiency alpha */
+    const int32_t *falloff;      /* [R] nullable: 0 none, 1 Lindemann, 2 Troe */
+    const double *falloff_params;/* [R*7] nullable (required with falloff) */
 } chem_mech_desc;
 
 typedef struct {

@@ -450,6 +450,22 @@ int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
             if (pr.first == k) return fail(c, CHEM_E_BAD_MECHANISM, "duplicate efficiency %d", i);
         eff[j].push_back({k, m->eff_value[i] - 1.0});
     }
+    // fall-off forms: third-body reactions only; finite parameters, A0 > 0,
+    // Troe T3, T1 > 0
+    bool any_fo = false;
+    if (m->falloff) {
+        if (!m->falloff_params) return fail(c, CHEM_E_BAD_MECHANISM, "falloff without falloff_params");
+        for (int j = 0; j < R; ++j) {
+            const int t = m->falloff[j];
+            if (t == 0) continue;
+            const double *f = m->falloff_params + 7 * (size_t)j;
+            bool ok = (t == 1 || t == 2) && is_tb[j] && f[0] > 0.0;
+            for (int i = 0; i < 7; ++i) ok = ok && isfinite(f[i]);
+            if (t == 2) ok = ok && f[4] > 0.0 && f[5] > 0.0;
+            if (!ok) return fail(c, CHEM_E_BAD_MECHANISM, "reaction %d: bad fall-off form", j);
+            any_fo = true;
+        }
+    }
 
     HIPCHK(c, hipSetDevice(c->device));
     free_mech(c);
@@ -512,6 +528,7 @@ int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
         }
         q.idx[0] = r0 | (r1 << 16);
         q.idx[1] = p0 | (p1 << 16);
+        if (any_fo && m->falloff[j]) tb |= TB_FALLOFF;
         q.idx[2] = p2 | (tb << 16);
         q.idx[3] = (snu + 8) | (es[0] << 8) | (es[1] << 16) | (es[2] << 24);
         q.lnA = log(m->A[j]);
@@ -519,15 +536,29 @@ int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
         q.EaR = m->Ea[j] / RU_J;
     }
 
+    // fall-off parameters by reaction slot (device order)
+    std::vector<double> fo(any_fo ? (size_t)R * FO_STRIDE : 1, 0.0);
+    if (any_fo)
+        for (int i = 0; i < R; ++i) {
+            const int j = ord[i].src;
+            if (!m->falloff[j]) continue;
+            const double *f = m->falloff_params + 7 * (size_t)j;
+            double *d = &fo[(size_t)i * FO_STRIDE];
+            d[0] = log(f[0]); d[1] = f[1]; d[2] = f[2] / RU_J;
+            d[3] = f[3]; d[4] = f[4]; d[5] = f[5]; d[6] = f[6];
+            d[7] = (double)m->falloff[j];
+        }
     MechDev &M = c->M;
     M = MechDev{};
+    M.has_fo = any_fo ? 1 : 0;
     M.N = N; M.R = R; M.n = N + 1;
     M.ldj = (M.n % 2) ? M.n : M.n + 1;
     int rc;
     if ((rc = upload(c, nasa_t, &M.nasa_t)) || (rc = upload(c, W, &M.W)) ||
         (rc = upload(c, invW, &M.invW)) || (rc = upload(c, spc, &M.spc)) ||
         (rc = upload(c, rxn, &M.rxn)) || (rc = upload(c, tb_ptr, &M.tb_ptr)) ||
-        (rc = upload(c, eff_sp, &M.eff_sp)) || (rc = upload(c, eff_am1, &M.eff_am1))) {
+        (rc = upload(c, eff_sp, &M.eff_sp)) || (rc = upload(c, eff_am1, &M.eff_am1)) ||
+        (rc = upload(c, fo, &M.fo))) {
         free_mech(c);
         return rc;
     }

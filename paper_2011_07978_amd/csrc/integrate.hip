@@ -70,7 +70,7 @@ __host__ __device__ inline int table_doubles(const MechDev &M) {
 // f(y), and with JAC the analytic Jacobian into LDS (row-major, stride ldj).
 // Returns f_r on lane r.  All lanes of the wave must call it.
 // -----------------------------------------------------------------------------
-template <bool JAC, bool LT>
+template <bool JAC, bool LT, bool FO>
 __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const double p,
                                            const double y, double *__restrict__ lds) {
     // The memory clobber keeps the descriptor loads, and the opaque lane index
@@ -142,7 +142,8 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
         const int ix0 = rec.idx[0], ix1 = rec.idx[1], ix2 = rec.idx[2], ix3 = rec.idx[3];
         const int r0 = ix0 & 0xffff, r1 = (int)((unsigned)ix0 >> 16);
         const int p0 = ix1 & 0xffff, p1 = (int)((unsigned)ix1 >> 16);
-        const int p2 = ix2 & 0xffff, tb = (int)((unsigned)ix2 >> 16);
+        const int p2 = ix2 & 0xffff, tbw = (int)((unsigned)ix2 >> 16);
+        const int tb = tbw & TB_CODE;
         const double snu = (double)((ix3 & 0xff) - 8);
         const int es0 = (ix3 >> 8) & 0xff, es1 = (ix3 >> 16) & 0xff;
         const int es2 = (int)((unsigned)ix3 >> 24);
@@ -161,6 +162,14 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
             const int e1 = M.tb_ptr[tb - TB_LIST0 + 1];
             for (int e = M.tb_ptr[tb - TB_LIST0]; e < e1; ++e) m += M.eff_am1[e] * Cl[M.eff_sp[e]];
         }
+        // fall-off: the rate constant is k_inf G([M], T) in place of k [M]
+        double dGdM = 1.0, dlnGdT = 0.0;
+        if (FO && (tbw & TB_FALLOFF)) {
+            double G;
+            falloff_eval(M.fo + (size_t)j * FO_STRIDE, T, invT, lnT, kf,
+                         bj * invT + EaRj * invT * invT, m, G, dGdM, dlnGdT);
+            m = G;
+        }
         const double Delta = valid ? kf * Pf - kr * Pr : 0.0;
         const double q = m * Delta;
         lds_add(wl + r0, -q);
@@ -169,7 +178,7 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
         lds_add(wl + p1, q);
         lds_add(wl + p2, q);
         if (JAC) {
-            const double dlnkf = bj * invT + EaRj * invT * invT;
+            const double dlnkf = bj * invT + EaRj * invT * invT + dlnGdT;
             const double dH = -hl[r0] - hl[r1] + hl[p0] + hl[p1] + hl[p2];
             const double dlnkr = dlnkf - (dH - snu) * invT;
             const double mkf = valid ? m * kf : 0.0, mkr = valid ? m * kr : 0.0;
@@ -188,7 +197,7 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
                 for (int b = 0; b < 5; ++b)
                     if (sl[b] < N) lds_add(row + 1 + sl[b], nu * ds[b]);
                 if (tb != TB_NONE) {
-                    const double nd = nu * Delta;
+                    const double nd = nu * Delta * dGdM;
                     lds_add(tbl + sa + 1, nd);
                     if (es0 < N) lds_add(row + 1 + es0, nd * e0v);
                     if (es1 < N) lds_add(row + 1 + es1, nd * e1v);
@@ -450,7 +459,7 @@ __device__ __forceinline__ void build_matrix(const MechDev *__restrict__ Mp,
 
 // One Rodas4 attempt of size h from y (f0 = f(y), J in LDS).  Returns false
 // when M is singular.  ynew and err are per lane.
-template <int NP, bool LT>
+template <int NP, bool LT, bool FO>
 __device__ __forceinline__ bool rodas_attempt(const MechDev *__restrict__ M, double p, double y,
                                               double f0, double h, double *lds, double &ynew,
                                               double &err) {
@@ -471,7 +480,7 @@ __device__ __forceinline__ bool rodas_attempt(const MechDev *__restrict__ M, dou
             ys += kRodasA[s][2] * u2;
             ys += kRodasA[s][3] * u3;
             ys += kRodasA[s][4] * u4;
-            rv = rhs_eval<false, LT>(M, p, ys, lds);
+            rv = rhs_eval<false, LT, FO>(M, p, ys, lds);
             rv += (kRodasC[s][0] / h) * u0;
             rv += (kRodasC[s][1] / h) * u1;
             rv += (kRodasC[s][2] / h) * u2;
@@ -527,7 +536,7 @@ __device__ __forceinline__ double *init_lds(const MechDev *Mp) {
 // -----------------------------------------------------------------------------
 // Adaptive integration of one cell over [0, dt]
 // -----------------------------------------------------------------------------
-template <int NP, bool LT>
+template <int NP, bool LT, bool FO>
 __device__ __forceinline__ void integrate_cell(const MechDev *__restrict__ M, const IntParams &P,
                                                int64_t cell, double *lds) {
     const int lane = lane_id();
@@ -556,14 +565,14 @@ __device__ __forceinline__ void integrate_cell(const MechDev *__restrict__ M, co
     double hnext = h, t = 0.0;
     int nacc = 0, nrej = 0, status = 0;
     bool rej_last = false;
-    double f0 = rhs_eval<true, LT>(M, p, y, lds);
+    double f0 = rhs_eval<true, LT, FO>(M, p, y, lds);
     while (t < dt) {
         if (nacc + nrej >= P.max_steps) { status = 1; break; }
         bool last = false;
         if (h >= dt - t) { h = dt - t; last = true; }
         if (h < P.hmin_frac * dt) { status = 2; break; }
         double ynew = 0.0, ev = 0.0;
-        const bool ok = rodas_attempt<NP, LT>(M, p, y, f0, h, lds, ynew, ev);
+        const bool ok = rodas_attempt<NP, LT, FO>(M, p, y, f0, h, lds, ynew, ev);
         double e = 0.0;
         bool bad = !ok;
         if (ok) {
@@ -581,7 +590,7 @@ __device__ __forceinline__ void integrate_cell(const MechDev *__restrict__ M, co
             hnext = uniform_d(h * fac);
             h = hnext;
             rej_last = false;
-            if (t < dt) f0 = rhs_eval<true, LT>(M, p, y, lds);
+            if (t < dt) f0 = rhs_eval<true, LT, FO>(M, p, y, lds);
         } else {
             const double fac = bad ? 0.2 : fmax(0.2, 0.9 * pow(e, -0.25));
             h = uniform_d(h * fac);
@@ -608,19 +617,19 @@ __device__ __forceinline__ void integrate_cell(const MechDev *__restrict__ M, co
 // Static launch: workgroup i (one wavefront) integrates cell i, reading the
 // records from global memory (an LDS copy per cell would cost more than it
 // saves).
-template <int NP>
+template <int NP, bool FO>
 __global__ __launch_bounds__(64) void k_integrate_plain(const MechDev *__restrict__ M, IntParams P) {
     double *lds = init_lds<false>(M);
     const int64_t cell = blockIdx.x;
     if (P.flags && P.flags[cell] >= 2) return;
-    integrate_cell<NP, false>(M, P, cell, lds);
+    integrate_cell<NP, false, FO>(M, P, cell, lds);
 }
 
 // Persistent wavefronts draw cells from NSEG segments of the heavy-first queue
 // (segment x holds sorted positions x, x + NSEG, ...); wavefront w starts on
 // segment w % NSEG and steals from the next segments once its own is drained.
 // Every wavefront exits after NSEG consecutive empty segments.
-template <int NP>
+template <int NP, bool FO>
 __global__ __launch_bounds__(256) void k_integrate_queue(const MechDev *__restrict__ M, IntParams P) {
     double *lds = init_lds<true>(M);
     const int wpb = (int)(blockDim.x >> 6);
@@ -664,7 +673,7 @@ __global__ __launch_bounds__(256) void k_integrate_queue(const MechDev *__restri
             cell = P.queue[first + NSEG * q];
             ++q;
         }
-        integrate_cell<NP, true>(M, P, cell, lds);
+        integrate_cell<NP, true, FO>(M, P, cell, lds);
     }
 }
 
@@ -678,7 +687,7 @@ __global__ __launch_bounds__(64) void k_eval_rhs_jac(const MechDev *__restrict__
     double y = 0.0;
     if (lane == 0) y = P.T[cell];
     else if (lane <= N) y = P.Y[(int64_t)(lane - 1) * P.ncells + cell];
-    const double f = rhs_eval<true, true>(M, P.p[cell], y, lds);
+    const double f = rhs_eval<true, true, true>(M, P.p[cell], y, lds);
     if (fout && lane < n) fout[cell * n + lane] = f;
     if (Jout)
         for (int i = lane; i < n * n; i += 64)
@@ -695,9 +704,9 @@ __global__ __launch_bounds__(64) void k_rodas_step(const MechDev *__restrict__ M
     if (lane == 0) y = P.T[cell];
     else if (lane <= N) y = P.Y[(int64_t)(lane - 1) * P.ncells + cell];
     const double p = P.p[cell];
-    const double f0 = rhs_eval<true, true>(M, p, y, lds);
+    const double f0 = rhs_eval<true, true, true>(M, p, y, lds);
     double ynew = 0.0, err = 0.0;
-    const bool ok = rodas_attempt<NP, true>(M, p, y, f0, h, lds, ynew, err);
+    const bool ok = rodas_attempt<NP, true, true>(M, p, y, f0, h, lds, ynew, err);
     if (!ok) { ynew = NAN; err = NAN; }
     if (lane < n) {
         ynew_out[cell * n + lane] = ynew;
@@ -731,20 +740,22 @@ static size_t lds_bytes(const MechDev &M, int wpb) {
 
 // Host launchers: M is the host copy (sizes), Md the device copy the kernels read.
 
-template <int NP>
+// Fall-off reactions get their own instantiation (FO), so that mechanisms
+// without them run code with no trace of the fall-off branch.
+template <int NP, bool FO>
 static hipError_t launch_integrate_np(const MechDev &M, const MechDev *Md, const IntParams &P,
                                       int schedule, int grid, hipStream_t s) {
     const int wpb = wave_kernel_wpb(M);
     const size_t sh = lds_bytes(M, wpb);
     if (schedule == 0) {
         const size_t sh1 = sizeof(double) * (size_t)M.lds_doubles;
-        hipFuncSetAttribute((const void *)k_integrate_plain<NP>,
+        hipFuncSetAttribute((const void *)k_integrate_plain<NP, FO>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh1);
-        hipLaunchKernelGGL(k_integrate_plain<NP>, dim3((unsigned)P.ncells), dim3(64), sh1, s, Md, P);
+        hipLaunchKernelGGL((k_integrate_plain<NP, FO>), dim3((unsigned)P.ncells), dim3(64), sh1, s, Md, P);
     } else {
-        hipFuncSetAttribute((const void *)k_integrate_queue<NP>,
+        hipFuncSetAttribute((const void *)k_integrate_queue<NP, FO>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-        hipLaunchKernelGGL(k_integrate_queue<NP>, dim3((unsigned)grid), dim3(64 * wpb), sh, s, Md, P);
+        hipLaunchKernelGGL((k_integrate_queue<NP, FO>), dim3((unsigned)grid), dim3(64 * wpb), sh, s, Md, P);
     }
     return hipGetLastError();
 }
@@ -752,7 +763,8 @@ static hipError_t launch_integrate_np(const MechDev &M, const MechDev *Md, const
 hipError_t launch_integrate(int NP, const MechDev &M, const MechDev *Md, const IntParams &P,
                             int schedule, int grid, hipStream_t s) {
     switch (NP) {
-#define CASE(v) case v: return launch_integrate_np<v>(M, Md, P, schedule, grid, s);
+#define CASE(v) case v: return M.has_fo ? launch_integrate_np<v, true>(M, Md, P, schedule, grid, s) \
+                                 : launch_integrate_np<v, false>(M, Md, P, schedule, grid, s);
         CHEM_NP_LIST(CASE)
 #undef CASE
     }
@@ -768,9 +780,9 @@ int queue_occupancy(int NP, const MechDev &M) {
     switch (NP) {
 #define CASE(v)                                                                                 \
     case v:                                                                                     \
-        hipFuncSetAttribute((const void *)k_integrate_queue<v>,                                 \
+        hipFuncSetAttribute((const void *)k_integrate_queue<v, false>,                          \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);               \
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_integrate_queue<v>, 64 * wpb, sh); \
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_integrate_queue<v, false>, 64 * wpb, sh); \
         break;
         CHEM_NP_LIST(CASE)
 #undef CASE

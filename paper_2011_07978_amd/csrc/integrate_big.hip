@@ -173,7 +173,8 @@ __device__ double rhs_big(const MechDev *__restrict__ Mp, const double p, const 
         const int ix0 = rec.idx[0], ix1 = rec.idx[1], ix2 = rec.idx[2], ix3 = rec.idx[3];
         const int r0 = ix0 & 0xffff, r1 = (int)((unsigned)ix0 >> 16);
         const int p0 = ix1 & 0xffff, p1 = (int)((unsigned)ix1 >> 16);
-        const int p2 = ix2 & 0xffff, tb = (int)((unsigned)ix2 >> 16);
+        const int p2 = ix2 & 0xffff, tbw = (int)((unsigned)ix2 >> 16);
+        const int tb = tbw & TB_CODE;
         const double snu = (double)((ix3 & 0xff) - 8);
         const int es0 = (ix3 >> 8) & 0xff, es1 = (ix3 >> 16) & 0xff;
         const int es2 = (int)((unsigned)ix3 >> 24);
@@ -192,11 +193,19 @@ __device__ double rhs_big(const MechDev *__restrict__ Mp, const double p, const 
             const int e1 = M.tb_ptr[tb - TB_LIST0 + 1];
             for (int e = M.tb_ptr[tb - TB_LIST0]; e < e1; ++e) m += M.eff_am1[e] * Cl[M.eff_sp[e]];
         }
+        // fall-off: the rate constant is k_inf G([M], T) in place of k [M]
+        double dGdM = 1.0, dlnGdT = 0.0;
+        if (tbw & TB_FALLOFF) {
+            double G;
+            falloff_eval(M.fo + (size_t)(valid ? j0 + tid : R - 1) * FO_STRIDE, T, invT, lnT, kf,
+                         bj * invT + EaRj * invT * invT, m, G, dGdM, dlnGdT);
+            m = G;
+        }
         const double Delta = kf * Pf - kr * Pr;
         const double q = m * Delta;
         double dqdT = 0.0, ds[5] = {0, 0, 0, 0, 0};
         if (JAC) {
-            const double dlnkf = bj * invT + EaRj * invT * invT;
+            const double dlnkf = bj * invT + EaRj * invT * invT + dlnGdT;
             const double dH = -hl[r0] - hl[r1] + hl[p0] + hl[p1] + hl[p2];
             const double dlnkr = dlnkf - (dH - snu) * invT;
             const double mkf = m * kf, mkr = m * kr;
@@ -227,7 +236,7 @@ __device__ double rhs_big(const MechDev *__restrict__ Mp, const double p, const 
                         for (int b = 0; b < 5; ++b)
                             if (sl[b] < N) lds_add_b(row + 1 + sl[b], nu * ds[b]);
                         if (tb != TB_NONE) {
-                            const double nd = nu * Delta;
+                            const double nd = nu * Delta * dGdM;
                             lds_add_b(tbl + sa + 1, nd);
                             if (es0 < N) lds_add_b(row + 1 + es0, nd * e0v);
                             if (es1 < N) lds_add_b(row + 1 + es1, nd * e1v);

@@ -17,6 +17,8 @@ constexpr int SPC_STRIDE = 18;
 
 // Reaction record (64 bytes).  idx[0] = r0 | r1 << 16, idx[1] = p0 | p1 << 16,
 // idx[2] = p2 | tb << 16, idx[3] = (sum_nu + 8) | es0 << 8 | es1 << 16 | es2 << 24.
+// Bit 15 of tb (TB_FALLOFF) marks a fall-off reaction, whose parameters are
+// in MechDev::fo at the reaction's slot.
 // Missing slots hold the sentinel species N.  tb = 0: no third body;
 // tb = 1: third body with up to three listed efficiencies stored inline
 // (alpha - 1 in eff[], species es0..es2, unused ones eff = 0, es = N);
@@ -27,6 +29,50 @@ struct RxnRec {
     int idx[4];
 };
 constexpr int TB_NONE = 0, TB_INLINE = 1, TB_LIST0 = 2;
+constexpr int TB_FALLOFF = 0x8000, TB_CODE = 0x7fff;
+
+// Fall-off parameters of one reaction slot (8 doubles): ln A0, b0, Ea0 / R,
+// Troe a, T3, T1, T2 (<= 0: no T2 term), form (1 Lindemann, 2 Troe).
+constexpr int FO_STRIDE = 8;
+
+// Fall-off factor (Lindemann, Troe) and its derivatives.  The rate constant is
+// k_inf G with Pr = k0 [M] / k_inf and G = Pr / (1 + Pr) F; F = 1 (Lindemann)
+// or Troe's broadening factor:
+//   Fcent = (1 - a) exp(-T/T3) + a exp(-T/T1) + exp(-T2/T),
+//   c = -0.4 - 0.67 log10 Fcent, n = 0.75 - 1.27 log10 Fcent, d = 0.14,
+//   f1 = x / (n - d x), x = log10 Pr + c,  log10 F = log10 Fcent / (1 + f1^2).
+// dGdM = dG/d[M]; dlnGdT = d ln G / dT at fixed [M] (dlnkinf = d ln k_inf / dT).
+__device__ __forceinline__ void falloff_eval(const double *__restrict__ f, double T, double invT,
+                                             double lnT, double kinf, double dlnkinf, double M,
+                                             double &G, double &dGdM, double &dlnGdT) {
+    const double k0 = exp(f[0] + f[1] * lnT - f[2] * invT);
+    const double r = k0 / kinf;
+    const double Pr = r * M;
+    const double inv1p = 1.0 / (1.0 + Pr);
+    double F = 1.0, S = 0.0, dlnF_dT = 0.0;
+    if (f[7] == 2.0) {
+        const double e3 = exp(-T / f[4]), e1 = exp(-T / f[5]);
+        const double e2 = f[6] > 0.0 ? exp(-f[6] * invT) : 0.0;
+        const double Fc = (1.0 - f[3]) * e3 + f[3] * e1 + e2;
+        const double dFc = -(1.0 - f[3]) / f[4] * e3 - f[3] / f[5] * e1 + f[6] * invT * invT * e2;
+        const double ln10 = 2.302585092994045684;
+        const double lFc = log(Fc) / ln10;
+        const double c = -0.4 - 0.67 * lFc, n = 0.75 - 1.27 * lFc;
+        const double x = log(Pr) / ln10 + c;
+        const double den = n - 0.14 * x;
+        const double f1 = x / den;
+        const double q = 1.0 / (1.0 + f1 * f1);
+        F = exp(ln10 * lFc * q);
+        S = -2.0 * lFc * f1 * q * q * n / (den * den);                 // d ln F / d ln Pr
+        const double df1_dlFc = (1.27 * x - 0.67 * n) / (den * den);
+        const double dlF_dlFc = q - 2.0 * lFc * f1 * q * q * df1_dlFc;
+        dlnF_dT = dlF_dlFc * dFc / Fc;                                 // at fixed Pr
+    }
+    G = Pr * inv1p * F;
+    dGdM = F * inv1p * (inv1p + S) * r;
+    const double dlnk0 = f[1] * invT + f[2] * invT * invT;
+    dlnGdT = (inv1p + S) * (dlnk0 - dlnkinf) + dlnF_dT;
+}
 
 // Loads through this cast are global-memory loads (not flat), so they do not
 // share a wait counter with LDS traffic.
@@ -46,6 +92,8 @@ struct MechDev {
     const int *tb_ptr;      // efficiency lists of third-body reactions with > 3 entries
     const int *eff_sp;
     const double *eff_am1;  // alpha - 1
+    const double *fo;       // [R][FO_STRIDE] fall-off parameters by reaction slot
+    int has_fo;             // any fall-off reaction
     // LDS layout (offsets in doubles)
     int off_J, off_q, off_C, off_g, off_h, off_e, off_cp, off_tb, off_sv, lds_doubles;
 };
