@@ -425,7 +425,7 @@ def main():
     # (profiles/k_integrate_queue_54__pmc_traffic_mapped_262k.md)
     traffic = None
     if kname == "k_integrate_queue" and mech.n_species == 53:
-        traffic = 8588.0 * float(np.mean([s["cells_integrated"] for s in st_h]))
+        traffic = 8610.0 * float(np.mean([s["cells_integrated"] for s in st_h]))
     roof = dict(bound="alu", achieved=achieved, peak=accounting.FP64_VECTOR_PEAK_TFLOPS,
                 unit="TFLOP/s", frac=achieved / accounting.FP64_VECTOR_PEAK_TFLOPS, traffic=traffic,
                 traffic_unit="bytes per launch" if traffic else None,
