@@ -33,3 +33,27 @@ def test_rhs_and_jacobian_with_falloff(name):
 @pytest.mark.parametrize("name", MECHS)
 def test_flow_step_with_falloff(name):
     _flow(name)
+
+
+def test_bad_falloff_descriptions_are_rejected():
+    import dataclasses
+
+    from paper_2011_07978_amd.chem import Chem, ChemError
+    from tests.gpu_util import say
+    base = synth.mechanism("mech53fo")
+    j_fo = int(np.nonzero(base.falloff == 2)[0][0])
+    j_plain = int(np.nonzero(base.third_body == 0)[0][0])
+    cases = []
+    t = base.falloff.copy(); t[j_plain] = 1                      # not a third-body reaction
+    cases.append(dataclasses.replace(base, falloff=t))
+    t = base.falloff.copy(); t[j_fo] = 3                          # unknown form
+    cases.append(dataclasses.replace(base, falloff=t))
+    for col, v in ((0, 0.0), (4, -1.0), (5, 0.0), (2, np.nan)):   # A0 <= 0, T3/T1 <= 0, NaN
+        prm = base.fo_params.copy(); prm[j_fo, col] = v
+        cases.append(dataclasses.replace(base, fo_params=prm))
+    for i, m in enumerate(cases):
+        say("bad fall-off case", i)
+        c = Chem(0)
+        with pytest.raises(ChemError):
+            c.set_mechanism(m)
+    Chem(0).set_mechanism(base)                                    # the valid one loads

@@ -252,3 +252,27 @@ def test_full_size_field_sampled_parity():
     print(rep, s, "mapped in sample", int((sub_flags == 2).sum()))
     assert rep["ok"], rep
     assert (sub_flags == 2).sum() > 0 and (sub_flags == 0).sum() > 0
+
+
+def test_static_blocks_with_mapping_and_slot_query():
+    """CHEM_SCHED_BLOCKS skips mapped cells like the other launches (results
+    equal the queue's bit for bit); the slot count needs a mechanism."""
+    from paper_2011_07978_amd.chem import Chem, ChemError
+    from tests.gpu_util import chem_for, dev, host, say
+    with pytest.raises(ChemError):
+        Chem(0).slots()
+    mech = synth.mechanism("mech53")
+    f = synth.field_mapped(20000, seed=41)
+    Yf, Yo = synth.stream_fuel(mech), synth.stream_oxidiser(mech)
+    outs = []
+    for sched in (CHEM_SCHED_QUEUE, CHEM_SCHED_BLOCKS):
+        c = chem_for(mech, schedule=sched)
+        assert c.slots() >= 256
+        say("mapped + schedule", sched)
+        T, p, Y = dev(f.T), dev(f.p), dev(f.Y)
+        flags, ref = c.map_reference(T, p, Y, Yf, Yo, 1e-4)
+        s = c.integrate(T, p, Y, f.dt, flags=flags, ref_index=ref, stats=True)
+        torch.cuda.synchronize()
+        assert s["cells_mapped"] > 0 and s["cells_mapped"] + s["cells_integrated"] == f.n_cells
+        outs.append((host(T), host(Y)))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])

@@ -141,3 +141,34 @@ def test_library_plan_matches_oracle():
         ops_l, after_l = chem.plan_balance(n_prob, t)
         assert ops_l == ops_o, seed
         assert np.array_equal(after_l, after_o), seed
+
+
+def test_library_planner_rejects_bad_input():
+    from paper_2011_07978_amd import chem
+    try:
+        L = chem.load_library()
+    except RuntimeError:
+        pytest.skip("libchem.so not built")
+    import ctypes as C
+    ops = (chem.BalanceOp * 4)()
+    n = C.c_int64(0)
+    cnt = np.array([2, 1], dtype=np.int64)
+    good = np.array([1.0, 2.0, 3.0])
+    P = lambda a, t: a.ctypes.data_as(C.POINTER(t))
+    # no processes, negative count, negative / non-finite cost, null output
+    assert L.chem_plan_balance(0, P(cnt, C.c_int64), P(good, C.c_double), 0.01, ops, 4, C.byref(n), None) != 0
+    bad_cnt = np.array([2, -1], dtype=np.int64)
+    assert L.chem_plan_balance(2, P(bad_cnt, C.c_int64), P(good, C.c_double), 0.01, ops, 4, C.byref(n), None) != 0
+    for v in (-1.0, np.inf, np.nan):
+        t = good.copy(); t[1] = v
+        assert L.chem_plan_balance(2, P(cnt, C.c_int64), P(t, C.c_double), 0.01, ops, 4, C.byref(n), None) != 0
+    assert L.chem_plan_balance(2, P(cnt, C.c_int64), P(good, C.c_double), 0.01, ops, 4, None, None) != 0
+    # too small an output array: error, but the count of operations is reported
+    heavy = np.array([1, 1, 1, 5], dtype=np.int64)
+    t = np.ones(8)
+    rc = L.chem_plan_balance(4, P(heavy, C.c_int64), P(t, C.c_double), 0.01, ops, 1, C.byref(n), None)
+    assert rc != 0 and n.value == 3
+    # one process: nothing to do
+    one = np.array([3], dtype=np.int64)
+    assert L.chem_plan_balance(1, P(one, C.c_int64), P(good, C.c_double), 0.01, ops, 4, C.byref(n), None) == 0
+    assert n.value == 0
