@@ -287,8 +287,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="surrogate", choices=["small", "flame", "mapped", "large",
-                                                             "surrogate", "unit", "mapping-study"],
+    ap.add_argument("--workload", default="surrogate",
+                    choices=["small", "flame", "flame_shuffled", "flame_hot_last", "mapped", "large",
+                             "surrogate", "unit", "mapping-study"],
                     help="unit: the load-balancing benchmark of Sec. 3 (layouts C1-C4); "
                          "mapping-study: mapped vs unmapped error over Z_tol and the T criterion")
     ap.add_argument("--unit-problems", type=int, default=100,

@@ -358,8 +358,11 @@ def field_small(n_cells=4096, seed=101) -> Field:
                  np.zeros(n_cells, np.int8), ("random",))
 
 
-def field_bimodal(mech_name="mech53", n_cells=65536, seed=102, dt=1e-6, shuffle=False) -> Field:
-    """10% hot igniting cells first (contiguous), 90% cold near-reactant cells."""
+def field_bimodal(mech_name="mech53", n_cells=65536, seed=102, dt=1e-6, shuffle=False,
+                  hot_last=False) -> Field:
+    """10% hot igniting cells first (contiguous), 90% cold near-reactant cells;
+    shuffle permutes the cells, hot_last puts the hot block at the end of the
+    index range (the worst order for a launch that starts cells in index order)."""
     mech = mechanism(mech_name)
     N = mech.n_species
     rng = _rng(seed)
@@ -376,6 +379,9 @@ def field_bimodal(mech_name="mech53", n_cells=65536, seed=102, dt=1e-6, shuffle=
     cls = np.concatenate([np.full(n_hot, 2, np.int8), np.zeros(n_cold, np.int8)])
     if shuffle:
         perm = rng.permutation(n_cells)
+        T, Y, cls = T[perm], Y[:, perm], cls[perm]
+    elif hot_last:
+        perm = np.concatenate([np.arange(n_hot, n_cells), np.arange(n_hot)])
         T, Y, cls = T[perm], Y[:, perm], cls[perm]
     return Field(T, np.full(n_cells, P_ATM), np.ascontiguousarray(Y), dt, 1, cls,
                  ("cold", "mixing", "igniting"))
@@ -439,6 +445,8 @@ def field_unit(layout, heavy, light, n_slots, n_per_slot, dt=1e-6):
 WORKLOADS = {
     "small": dict(mech="small", field=lambda n=4096: field_small(n)),
     "flame": dict(mech="mech53", field=lambda n=65536: field_bimodal("mech53", n, 102)),
+    "flame_shuffled": dict(mech="mech53", field=lambda n=65536: field_bimodal("mech53", n, 102, shuffle=True)),
+    "flame_hot_last": dict(mech="mech53", field=lambda n=65536: field_bimodal("mech53", n, 102, hot_last=True)),
     "mapped": dict(mech="mech53", field=lambda n=262144: field_mapped(n, 103)),
     "large": dict(mech="mech130", field=lambda n=131072: field_bimodal("mech130", n, 104, dt=2e-6)),
     "surrogate": dict(mech="mech53", field=lambda n=1048576: field_mapped(n, 105, n_steps=1)),
