@@ -64,6 +64,10 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t *__restrict__ A,
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int m0 = blockIdx.x * 64 + (w >> 1) * 32, n0 = blockIdx.y * 64 + (w & 1) * 32;
     const int r16 = lane & 15, kq = (lane >> 4) * 8;
+    // split-K launches (gridDim.z > 1): slice z covers k in [zK, (z+1)K) and
+    // writes its partial product to its own M x ldc slab of C
+    A += (size_t)blockIdx.z * K;
+    B += (size_t)blockIdx.z * K;
     f32x4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -106,7 +110,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t *__restrict__ A,
                 } else if (EPI == EPI_OUT_T) {
                     e.C[(size_t)col * e.ldc + row] = v + e.bias[col];
                 } else {
-                    e.C[(size_t)row * e.ldc + col] = v;
+                    e.C[((size_t)blockIdx.z * M + row) * e.ldc + col] = v;
                 }
             }
 }
@@ -116,6 +120,15 @@ static void gemm(const uint16_t *A, int lda, const uint16_t *B, int ldb, int M, 
                  const GemmEpi &e, hipStream_t s) {
     dim3 grid((M + 63) / 64, (N + 63) / 64);
     hipLaunchKernelGGL(k_gemm_nt<EPI>, grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, e);
+}
+
+// dst[i] = sum over z of part[z][i], slices added in order
+__global__ __launch_bounds__(256) void k_sum_slices(const float *part, int S, int64_t n, float *dst) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.0f;
+    for (int z = 0; z < S; ++z) s += part[(size_t)z * n + i];
+    dst[i] = s;
 }
 
 // ------------------------------------------------------------- features ----
@@ -210,7 +223,7 @@ __global__ __launch_bounds__(256) void k_build_rows(FeatSrc f, TgtSrc t, const i
 // dO = 2 (out - target) / (B * nout) for the first nout columns, 0 elsewhere
 __global__ __launch_bounds__(256) void k_out_grad(const float *out, const float *Tg, int B, int nout,
                                                   float *dOf, uint16_t *dZ, uint16_t *dZT, int ldt,
-                                                  double *loss) {
+                                                  double *loss_part) {
     const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int c = threadIdx.x & 63;
     float g = 0.0f;
@@ -226,8 +239,26 @@ __global__ __launch_bounds__(256) void k_out_grad(const float *out, const float 
         dZ[(size_t)r * S_OUT + c] = gb;
         dZT[(size_t)c * ldt + r] = gb;
     }
+    // squared errors of the block's rows, added to the block's own running sum
     for (int m = 32; m > 0; m >>= 1) l2 += __shfl_xor(l2, m);
-    if ((threadIdx.x & 63) == 0 && l2 != 0.0) atomicAdd(loss, l2);
+    __shared__ double sh[4];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = l2;
+    __syncthreads();
+    if (threadIdx.x == 0) loss_part[blockIdx.x] += (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// loss[0] = sum of the n per-block running sums (one block, fixed order)
+__global__ __launch_bounds__(256) void k_sum_loss(const double *part, int n, double *loss) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+    __shared__ double sh[256];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[0] = sh[0];
 }
 
 // dZ = dH * GELU'(Z), as f32 (for the bias gradient) and bf16 (+ transpose)
@@ -248,6 +279,9 @@ __global__ __launch_bounds__(256) void k_gelu_back(const float *dH, const float 
 // (four row phases per block, combined in order); then one thread per column
 // adds the CS_CHUNKS partial sums in order.
 constexpr int CS_CHUNKS = 64;
+// slices of a split-K weight gradient: at most 256 workgroups of 64 x 64
+// outputs, so S M N <= 256 * 4096
+constexpr int64_t kSplitFloats = (int64_t)256 * 4096;
 __global__ __launch_bounds__(256) void k_colsum_part(const float *src, int B, int ncol, float *part) {
     const int c = blockIdx.x * 64 + (threadIdx.x & 63), ph = threadIdx.x >> 6;
     float s = 0.0f;
@@ -699,6 +733,9 @@ int Surrogate::reserve_ws(int B, bool training, char *err) {
         SCHK(get16(&dZb, (size_t)B * S_HID));
         SCHK(get16(&dZbT, (size_t)B * S_HID));
         SCHK(get32(&csum, (size_t)CS_CHUNKS * S_HID));
+        SCHK(get32(&kpart, (size_t)kSplitFloats));
+        double *dp = nullptr;
+        SCHK(dalloc(&dp, (size_t)(B + 3) / 4)); ws.push_back(dp); lpart = dp;
     }
     int *ip = nullptr;
     SCHK(dalloc(&ip, (size_t)B)); ws.push_back(ip); idx = ip;
@@ -739,16 +776,40 @@ void Surrogate::colsum(const float *src, int B, int ncol, float *dst, hipStream_
     hipLaunchKernelGGL(k_colsum_final, dim3((ncol + 255) / 256), dim3(256), 0, s, csum, ncol, dst);
 }
 
+// C [M x N], leading dimension N, = A B^T for a weight gradient: M x N is a
+// few tiles and K (the batch) is long, so the K range is cut into S slices
+// that fill the chip; each slice writes its partial product and a second pass
+// adds the slices in order
+void Surrogate::gemm_wgrad(const uint16_t *A, int lda, const uint16_t *Bm, int ldb, int M, int N,
+                           int K, float *C, hipStream_t s) {
+    const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
+    int S = 1;
+    while (tiles * 2 * S <= 256 && K % (64 * S) == 0 && K / (2 * S) >= 128 &&
+           (int64_t)2 * S * M * N <= kSplitFloats)
+        S *= 2;
+    GemmEpi e{};
+    e.ldc = N;
+    if (S == 1) {
+        e.C = C;
+        gemm<EPI_PLAIN>(A, lda, Bm, ldb, M, N, K, e, s);
+        return;
+    }
+    e.C = kpart;
+    hipLaunchKernelGGL(k_gemm_nt<EPI_PLAIN>, dim3((M + 63) / 64, (N + 63) / 64, S), dim3(256), 0, s,
+                       A, lda, Bm, ldb, M, N, K / S, e);
+    const int64_t mn = (int64_t)M * N;
+    hipLaunchKernelGGL(k_sum_slices, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s, kpart, S,
+                       mn, C);
+}
+
 // gradients of the mean-squared error for the B rows in X / Tg into G
 void Surrogate::backward(int B, hipStream_t s) {
     const int nout = N + 1;
     hipLaunchKernelGGL(k_out_grad, dim3((B + 3) / 4), dim3(256), 0, s, out, Tg, B, nout, dOf, dZ5,
-                       dZ5T, B, d_loss);
+                       dZ5T, B, lpart);
     // output layer
     {
-        GemmEpi e{};
-        e.C = G + layer_offset(4); e.ldc = S_HID;
-        gemm<EPI_PLAIN>(dZ5T, B, HT[3], B, S_OUT, S_HID, B, e, s);          // dW5 = dZ5^T H4
+        gemm_wgrad(dZ5T, B, HT[3], B, S_OUT, S_HID, B, G + layer_offset(4), s);   // dW5 = dZ5^T H4
         colsum(dOf, B, S_OUT, G + layer_offset(4) + (int64_t)S_OUT * S_HID, s);
         GemmEpi e2{};
         e2.C = dH; e2.ldc = S_HID;
@@ -758,10 +819,8 @@ void Surrogate::backward(int B, hipStream_t s) {
         hipLaunchKernelGGL(k_gelu_back, dim3((B * S_HID + 255) / 256), dim3(256), 0, s, dH, Z[l], B,
                            dZf, dZb, dZbT, B);
         const int ni = layer_in(l);
-        GemmEpi e{};
-        e.C = G + layer_offset(l); e.ldc = ni;
         const uint16_t *inT = l == 0 ? XT : HT[l - 1];
-        gemm<EPI_PLAIN>(dZbT, B, inT, B, S_HID, ni, B, e, s);               // dW = dZ^T h_{l-1}
+        gemm_wgrad(dZbT, B, inT, B, S_HID, ni, B, G + layer_offset(l), s);   // dW = dZ^T h_{l-1}
         colsum(dZf, B, S_HID, G + layer_offset(l) + (int64_t)S_HID * ni, s);
         if (l > 0) {
             GemmEpi e2{};
@@ -854,7 +913,7 @@ int Surrogate::train(const FeatSrc &f, const TgtSrc &t, int epochs, int B, doubl
         std::iota(perm.begin(), perm.end(), 0);
         std::shuffle(perm.begin(), perm.end(), rng);
         SCHK(hipMemcpyAsync(d_perm, perm.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
-        SCHK(hipMemsetAsync(d_loss, 0, sizeof(double), s));
+        SCHK(hipMemsetAsync(lpart, 0, sizeof(double) * ((B + 3) / 4), s));
         for (int64_t bi = 0; bi < nb; ++bi, ++step) {
             hipLaunchKernelGGL(k_build_rows, dim3((B + 3) / 4), dim3(256), 0, s, f, t,
                                d_perm + bi * B, (int64_t)0, B, P + weights_count(), X, XT, B, Tg);
@@ -869,6 +928,7 @@ int Surrogate::train(const FeatSrc &f, const TgtSrc &t, int epochs, int B, doubl
             int r2 = refresh(s, err);
             if (r2) return r2;
         }
+        hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(256), 0, s, lpart, (B + 3) / 4, d_loss);
         double l = 0.0;
         SCHK(hipMemcpyAsync(&l, d_loss, sizeof(double), hipMemcpyDeviceToHost, s));
         SCHK(hipStreamSynchronize(s));
@@ -888,11 +948,12 @@ int Surrogate::loss_grad(const FeatSrc &f, const TgtSrc &t, float *grad_host, do
     if (B % 64 != 0 || B < 64 || B > 65536) { snprintf(err, 256, "n must be a multiple of 64, <= 65536"); return -1; }
     int rc = reserve_ws(B, true, err);
     if (rc) return rc;
-    SCHK(hipMemsetAsync(d_loss, 0, sizeof(double), s));
+    SCHK(hipMemsetAsync(lpart, 0, sizeof(double) * ((B + 3) / 4), s));
     hipLaunchKernelGGL(k_build_rows, dim3((B + 3) / 4), dim3(256), 0, s, f, t, (const int *)nullptr,
                        (int64_t)0, B, P + weights_count(), X, XT, B, Tg);
     forward(B, true, false, s);
     backward(B, s);
+    hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(256), 0, s, lpart, (B + 3) / 4, d_loss);
     SCHK(hipMemcpyAsync(grad_host, G, sizeof(float) * weights_count(), hipMemcpyDeviceToHost, s));
     double l = 0.0;
     SCHK(hipMemcpyAsync(&l, d_loss, sizeof(double), hipMemcpyDeviceToHost, s));

@@ -55,6 +55,8 @@ struct Surrogate {
     float *Z[4] = {}, *out = nullptr, *Tg = nullptr, *dOf = nullptr, *dH = nullptr, *dZf = nullptr;
     uint16_t *dZ5 = nullptr, *dZ5T = nullptr, *dZb = nullptr, *dZbT = nullptr;
     float *csum = nullptr;   // partial column sums of the bias gradients
+    float *kpart = nullptr;  // split-K slices of the weight gradients
+    double *lpart = nullptr; // per-block running sums of the squared error
     int *idx = nullptr;
     int *sel_cnt = nullptr;  // rows selected for inference
 
@@ -67,6 +69,8 @@ struct Surrogate {
     void forward(int B, bool training, bool out_transposed, hipStream_t s);
     void backward(int B, hipStream_t s);
     void colsum(const float *src, int B, int ncol, float *dst, hipStream_t s);
+    void gemm_wgrad(const uint16_t *A, int lda, const uint16_t *Bm, int ldb, int M, int N, int K,
+                    float *C, hipStream_t s);
     int compute_norm(const FeatSrc &f, const TgtSrc &t, hipStream_t s, char *err);
     int train(const FeatSrc &f, const TgtSrc &t, int epochs, int B, double lr0, double lr1,
               uint64_t seed, float *loss_hist, int verbose, hipStream_t s, char *err);

@@ -66,11 +66,13 @@ def test_forward_matches_bf16_oracle():
     assert err.mean() < 0.25 * np.abs(exact - emu)[:, live].mean()
 
 
-def test_loss_gradient_matches_oracle():
+@pytest.mark.parametrize("n", [256, 4096])
+def test_loss_gradient_matches_oracle(n):
+    """256 rows: weight gradients in two K slices; 4096 rows (the training
+    batch): sixteen slices and 1024 per-block loss sums."""
     from tests.gpu_util import chem_for, dev, say
     mech = synth.mechanism("mech53")
     N = mech.n_species
-    n = 256
     f = _cells(n, 41)
     dt = synth.surrogate_dt(n, 42)
     rng = np.random.default_rng(43)
