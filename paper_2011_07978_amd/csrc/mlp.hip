@@ -261,19 +261,6 @@ __global__ __launch_bounds__(256) void k_sum_loss(const double *part, int n, dou
     if (threadIdx.x == 0) loss[0] = sh[0];
 }
 
-// dZ = dH * GELU'(Z), as f32 (for the bias gradient) and bf16 (+ transpose)
-__global__ __launch_bounds__(256) void k_gelu_back(const float *dH, const float *Z, int B,
-                                                   float *dZf, uint16_t *dZ, uint16_t *dZT, int ldt) {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= (int64_t)B * S_HID) return;
-    const int r = (int)(t / S_HID), c = (int)(t % S_HID);
-    const float g = dH[t] * gelu_df(Z[t]);
-    dZf[t] = g;
-    const uint16_t gb = f2bf(g);
-    dZ[t] = gb;
-    dZT[(size_t)c * ldt + r] = gb;
-}
-
 // Column sums of src [B x ncol] (bias gradients) in two fixed-order passes:
 // block (x, y) sums rows y, y + CS_CHUNKS, ... of 64 columns into part[y][c]
 // (four row phases per block, combined in order); then one thread per column
@@ -294,6 +281,29 @@ __global__ __launch_bounds__(256) void k_colsum_part(const float *src, int B, in
         part[(size_t)blockIdx.y * ncol + c] = (sh[0][threadIdx.x] + sh[1][threadIdx.x]) +
                                               (sh[2][threadIdx.x] + sh[3][threadIdx.x]);
 }
+// dZ = dH * GELU'(Z) of a hidden layer as bf16 (+ transpose) and the partial
+// column sums of the FP32 dZ (the bias gradient): block (x, y) covers 64
+// columns and visits rows in the order of k_colsum_part, so the partial sums
+// are the ones k_colsum_part would form from an FP32 copy of dZ
+__global__ __launch_bounds__(256) void k_gelu_back(const float *dH, const float *Z, int B,
+                                                   uint16_t *dZ, uint16_t *dZT, int ldt, float *part) {
+    const int c = blockIdx.x * 64 + (threadIdx.x & 63), ph = threadIdx.x >> 6;
+    float s = 0.0f;
+    for (int r = blockIdx.y + CS_CHUNKS * ph; r < B; r += 4 * CS_CHUNKS) {
+        const size_t t = (size_t)r * S_HID + c;
+        const float g = dH[t] * gelu_df(Z[t]);
+        s += g;
+        const uint16_t gb = f2bf(g);
+        dZ[t] = gb;
+        dZT[(size_t)c * ldt + r] = gb;
+    }
+    __shared__ float sh[4][64];
+    sh[ph][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (ph == 0)
+        part[(size_t)blockIdx.y * S_HID + c] = (sh[0][threadIdx.x] + sh[1][threadIdx.x]) +
+                                               (sh[2][threadIdx.x] + sh[3][threadIdx.x]);
+}
 __global__ __launch_bounds__(256) void k_colsum_final(const float *part, int ncol, float *dst) {
     const int c = blockIdx.x * 256 + threadIdx.x;
     if (c >= ncol) return;
@@ -302,9 +312,18 @@ __global__ __launch_bounds__(256) void k_colsum_final(const float *part, int nco
     dst[c] = s;
 }
 
+// where each layer's weights sit in the FP32 blob and their bf16 copies
+struct WeightCopies {
+    int64_t off[5];
+    int no[5], ni[5];
+    uint16_t *Wb[5], *WbT[5];
+};
+
+// Adam on the FP32 masters; a weight (not a bias) is also written to its
+// layer's bf16 copy Wb [no x ni] and transpose WbT [ni x no]
 __global__ __launch_bounds__(256) void k_adam(float *P, const float *G, float *m, float *v, int64_t n,
                                               float lr, float b1, float b2, float eps, float c1,
-                                              float c2) {
+                                              float c2, WeightCopies wc) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     const float g = G[i];
@@ -312,7 +331,21 @@ __global__ __launch_bounds__(256) void k_adam(float *P, const float *G, float *m
     const float vi = b2 * v[i] + (1.0f - b2) * g * g;
     m[i] = mi;
     v[i] = vi;
-    P[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    const float p = P[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    P[i] = p;
+    int64_t off = wc.off[0];
+    int no = wc.no[0], ni = wc.ni[0];
+    uint16_t *wb = wc.Wb[0], *wbt = wc.WbT[0];
+#pragma unroll
+    for (int q = 1; q < 5; ++q)
+        if (i >= wc.off[q]) { off = wc.off[q]; no = wc.no[q]; ni = wc.ni[q]; wb = wc.Wb[q]; wbt = wc.WbT[q]; }
+    const int64_t t = i - off;
+    if (t < (int64_t)no * ni) {
+        const int o = (int)(t / ni), k = (int)(t % ni);
+        const uint16_t b = f2bf(p);
+        wb[t] = b;
+        wbt[(size_t)k * no + o] = b;
+    }
 }
 
 // bf16 copies of a layer's weights: Wb [no x ni] and WbT [ni x no]
@@ -729,7 +762,6 @@ int Surrogate::reserve_ws(int B, bool training, char *err) {
         SCHK(get16(&dZ5, (size_t)B * S_OUT));
         SCHK(get16(&dZ5T, (size_t)B * S_OUT));
         SCHK(get32(&dH, (size_t)B * S_HID));
-        SCHK(get32(&dZf, (size_t)B * S_HID));
         SCHK(get16(&dZb, (size_t)B * S_HID));
         SCHK(get16(&dZbT, (size_t)B * S_HID));
         SCHK(get32(&csum, (size_t)CS_CHUNKS * S_HID));
@@ -816,12 +848,13 @@ void Surrogate::backward(int B, hipStream_t s) {
         gemm<EPI_PLAIN>(dZ5, S_OUT, WbT[4], S_OUT, B, S_HID, S_OUT, e2, s);    // dH4 = dZ5 W5
     }
     for (int l = 3; l >= 0; --l) {
-        hipLaunchKernelGGL(k_gelu_back, dim3((B * S_HID + 255) / 256), dim3(256), 0, s, dH, Z[l], B,
-                           dZf, dZb, dZbT, B);
+        hipLaunchKernelGGL(k_gelu_back, dim3(S_HID / 64, CS_CHUNKS), dim3(256), 0, s, dH, Z[l], B,
+                           dZb, dZbT, B, csum);
         const int ni = layer_in(l);
         const uint16_t *inT = l == 0 ? XT : HT[l - 1];
         gemm_wgrad(dZbT, B, inT, B, S_HID, ni, B, G + layer_offset(l), s);   // dW = dZ^T h_{l-1}
-        colsum(dZf, B, S_HID, G + layer_offset(l) + (int64_t)S_HID * ni, s);
+        hipLaunchKernelGGL(k_colsum_final, dim3(1), dim3(256), 0, s, csum, S_HID,
+                           G + layer_offset(l) + (int64_t)S_HID * ni);
         if (l > 0) {
             GemmEpi e2{};
             e2.C = dH; e2.ldc = S_HID;
@@ -909,6 +942,14 @@ int Surrogate::train(const FeatSrc &f, const TgtSrc &t, int epochs, int B, doubl
     std::mt19937_64 rng(seed ^ 0x9e3779b97f4a7c15ull);
     int64_t step = 0;
     const int64_t nw = weights_count();
+    WeightCopies wc{};
+    for (int l = 0; l < 5; ++l) {
+        wc.off[l] = layer_offset(l);
+        wc.no[l] = layer_out(l);
+        wc.ni[l] = layer_in(l);
+        wc.Wb[l] = Wb[l];
+        wc.WbT[l] = WbT[l];
+    }
     for (int ep = 0; ep < epochs; ++ep) {
         std::iota(perm.begin(), perm.end(), 0);
         std::shuffle(perm.begin(), perm.end(), rng);
@@ -924,9 +965,7 @@ int Surrogate::train(const FeatSrc &f, const TgtSrc &t, int epochs, int B, doubl
             const float b1 = 0.9f, b2 = 0.999f;
             const float c1 = 1.0f - powf(b1, (float)(step + 1)), c2 = 1.0f - powf(b2, (float)(step + 1));
             hipLaunchKernelGGL(k_adam, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, P, G, mA,
-                               vA, nw, lr, b1, b2, 1e-8f, c1, c2);
-            int r2 = refresh(s, err);
-            if (r2) return r2;
+                               vA, nw, lr, b1, b2, 1e-8f, c1, c2, wc);
         }
         hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(256), 0, s, lpart, (B + 3) / 4, d_loss);
         double l = 0.0;

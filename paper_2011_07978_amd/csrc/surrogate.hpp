@@ -52,7 +52,7 @@ struct Surrogate {
     bool ws_training = false;
     std::vector<void *> ws;
     uint16_t *X = nullptr, *XT = nullptr, *H[4] = {}, *HT[4] = {};
-    float *Z[4] = {}, *out = nullptr, *Tg = nullptr, *dOf = nullptr, *dH = nullptr, *dZf = nullptr;
+    float *Z[4] = {}, *out = nullptr, *Tg = nullptr, *dOf = nullptr, *dH = nullptr;
     uint16_t *dZ5 = nullptr, *dZ5T = nullptr, *dZb = nullptr, *dZbT = nullptr;
     float *csum = nullptr;   // partial column sums of the bias gradients
     float *kpart = nullptr;  // split-K slices of the weight gradients
