@@ -84,6 +84,14 @@ def test_plan_balanced_input_moves_nothing():
     assert ops == [] and list(after) == [4.0, 4.0, 4.0]
 
 
+def test_plan_without_load_moves_nothing():
+    """No problems anywhere, or only zero-cost ones: the mean load is zero,
+    every process already sits at it, and the walk ends without operations."""
+    for n_prob, t in (([0, 0, 0], []), ([2, 0, 1], [0.0, 0.0, 0.0])):
+        ops, after = balance.plan_balance(n_prob, t)
+        assert ops == [] and list(after) == [0.0, 0.0, 0.0]
+
+
 def test_plan_small_imbalance_is_not_emitted():
     """dL below 1 % of the mean load is planned but not sent."""
     ops, _ = balance.plan_balance([100, 100], [1.0] * 100 + [1.0] * 99 + [1.5])
@@ -168,6 +176,10 @@ def test_library_planner_rejects_bad_input():
     t = np.ones(8)
     rc = L.chem_plan_balance(4, P(heavy, C.c_int64), P(t, C.c_double), 0.01, ops, 1, C.byref(n), None)
     assert rc != 0 and n.value == 3
+    # no load at all: nothing to do
+    zero = np.array([0, 0, 0], dtype=np.int64)
+    assert L.chem_plan_balance(3, P(zero, C.c_int64), None, 0.01, ops, 4, C.byref(n), None) == 0
+    assert n.value == 0
     # one process: nothing to do
     one = np.array([3], dtype=np.int64)
     assert L.chem_plan_balance(1, P(one, C.c_int64), P(good, C.c_double), 0.01, ops, 4, C.byref(n), None) == 0
