@@ -97,6 +97,11 @@ class Oracle:
         if rc != 0:
             raise RuntimeError("orc_mech_create failed")
         self.h = h
+        pl_n = getattr(mech, "plog_count", None)
+        if pl_n is not None:
+            self._keep += [_i(pl_n), _f64(mech.plog_params)]
+            if L.orc_mech_set_plog(h, _p(self._keep[-2], _i32), _p(self._keep[-1])) != 0:
+                raise RuntimeError("orc_mech_set_plog failed")
 
     def __del__(self):
         try:
@@ -109,6 +114,13 @@ class Oracle:
         cp, h, s = (np.zeros(self.N) for _ in range(3))
         lib().orc_thermo(self.h, C.c_double(T), _p(cp), _p(h), _p(s))
         return cp, h, s
+
+    def ln_kf(self, j, T, p):
+        """ln k_f of reaction j at (T, p): Arrhenius, or for a PLOG reaction
+        the interpolation in ln p of its tabulated rate expressions."""
+        f = lib().orc_ln_kf
+        f.restype = C.c_double
+        return f(self.h, C.c_int(int(j)), C.c_double(T), C.c_double(p))
 
     def falloff_factor(self, j, T, M):
         """G of reaction j (its rate constant is k_inf G); [M] itself when j has

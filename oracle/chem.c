@@ -12,24 +12,33 @@
 #define SC_LOG log
 #define FN_RHS rhs_real
 #define FN_FALLOFF falloff_real
+#define FN_LNKF lnkf_real
 #include "rhs_body.h"
 #undef SC
 #undef SC_EXP
 #undef SC_LOG
 #undef FN_RHS
 #undef FN_FALLOFF
+#undef FN_LNKF
 
 #define SC double complex
 #define SC_EXP cexp
 #define SC_LOG clog
 #define FN_RHS rhs_cplx
 #define FN_FALLOFF falloff_cplx
+#define FN_LNKF lnkf_cplx
 #include "rhs_body.h"
 #undef SC
 #undef SC_EXP
 #undef SC_LOG
 #undef FN_RHS
 #undef FN_FALLOFF
+#undef FN_LNKF
+
+double orc_ln_kf(const omech *m, int j, double T, double p)
+{
+    return lnkf_real(m, j, p, T, log(T));
+}
 
 double orc_falloff_factor(const omech *m, int j, double T, double M)
 {
@@ -125,7 +134,7 @@ void orc_kinetics(const omech *m, double T, double p, const double *Y,
     const double lnT = log(T), ln_patm_RT = log(ORC_P_ATM / (ORC_RU_ERG * T));
     for (int j = 0; j < R; ++j) {
         const int *rs = m->reac + 2 * j, *ps = m->prod + 3 * j;
-        double ln_kf = m->lnA[j] + m->b[j] * lnT - m->Ea[j] / (ORC_RU_J * T);
+        double ln_kf = lnkf_real(m, j, p, T, lnT);
         double dG = 0.0, Pf = 1.0, Pr = 1.0;
         for (int s2 = 0; s2 < 2; ++s2) if (rs[s2] >= 0) { dG -= g[rs[s2]]; Pf *= C[rs[s2]]; }
         for (int s3 = 0; s3 < 3; ++s3) if (ps[s3] >= 0) { dG += g[ps[s3]]; Pr *= C[ps[s3]]; }
@@ -151,7 +160,7 @@ void orc_kinetics(const omech *m, double T, double p, const double *Y,
  * JCT = d omega / dT at fixed C, then the transformation to (T, Y). */
 void orc_jac(const omech *m, double p, const double *y, double *J)
 {
-    if (m->has_falloff) {
+    if (m->has_falloff || m->has_plog) {
         orc_jac_cs(m, p, y, J);
         return;
     }

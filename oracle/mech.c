@@ -57,9 +57,28 @@ int orc_mech_create(omech **out, int E, int N, int R,
     return 0;
 }
 
+int orc_mech_set_plog(omech *m, const int32_t *count, const double *params)
+{
+    const int R = m->R;
+    free(m->plog_n); free(m->plog);
+    m->plog_n = (int *)calloc((size_t)R, sizeof(int));
+    m->plog = (double *)calloc((size_t)R * 32, sizeof(double));
+    if (!m->plog_n || !m->plog) return -1;
+    m->has_plog = 0;
+    for (int j = 0; j < R; ++j) {
+        if (!count[j]) continue;
+        if (count[j] < 2 || count[j] > 8) return -1;
+        m->plog_n[j] = count[j];
+        for (int c = 0; c < 4 * count[j]; ++c) m->plog[(size_t)32 * j + c] = params[(size_t)32 * j + c];
+        m->has_plog = 1;
+    }
+    return 0;
+}
+
 void orc_mech_destroy(omech *m)
 {
     if (!m) return;
+    free(m->plog_n); free(m->plog);
     free(m->elem_mass); free(m->comp); free(m->W); free(m->nasa);
     free(m->reac); free(m->prod); free(m->lnA); free(m->b); free(m->Ea);
     free(m->tb); free(m->alpha); free(m->sum_nu); free(m->fo_type); free(m->fo);

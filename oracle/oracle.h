@@ -51,6 +51,9 @@ typedef struct omech {
     int    *fo_type;     /* [R] fall-off form: 0 none, 1 Lindemann, 2 Troe */
     double *fo;          /* [R*7] A0, b0, Ea0 (J/mol), a, T3, T1, T2 (T2 <= 0: no T2 term) */
     int    has_falloff;
+    int    *plog_n;      /* [R] pressure-dependent (PLOG) reactions: number of tabulated pressures, else 0 */
+    double *plog;        /* [R*32] up to 8 entries p_i (dyn/cm^2, increasing), A_i, b_i, Ea_i (J/mol) */
+    int    has_plog;
 } omech;
 
 typedef struct {
@@ -74,6 +77,11 @@ int  orc_mech_create(omech **out, int E, int N, int R,
                      const int32_t *eff_s, const double *eff_v,
                      const int32_t *fo_type, const double *fo_params);
 void orc_mech_destroy(omech *m);
+/* tabulated pressure dependence (PLOG) of the reactions with count[j] > 0:
+ * count[j] in 2..8 entries params[32j + 4i ..] = p_i, A_i, b_i, Ea_i */
+int  orc_mech_set_plog(omech *m, const int32_t *count, const double *params);
+/* ln k_f of reaction j at (T, p) (Arrhenius, or interpolated for PLOG) */
+double orc_ln_kf(const omech *m, int j, double T, double p);
 /* fall-off factor G(T, [M]) of reaction j: its rate constant is k_inf G */
 double orc_falloff_factor(const omech *m, int j, double T, double M);
 
@@ -87,7 +95,7 @@ void orc_kinetics(const omech *m, double T, double p, const double *Y,
 /* right-hand side f(y), y = (T, Y_1..Y_N) */
 void orc_rhs(const omech *m, double p, const double *y, double *f);
 /* analytic Jacobian, row-major n x n, J[i*n + j] = d f_i / d y_j (for
- * mechanisms with fall-off reactions: the complex-step Jacobian) */
+ * mechanisms with fall-off or PLOG reactions: the complex-step Jacobian) */
 void orc_jac(const omech *m, double p, const double *y, double *J);
 /* complex-step Jacobian (step 1e-30 i), same layout */
 void orc_jac_cs(const omech *m, double p, const double *y, double *J);

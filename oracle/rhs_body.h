@@ -2,11 +2,15 @@
  *
  * Included twice by chem.c: once with SC = double and once with
  * SC = double complex (for the complex-step Jacobian), so both evaluate the
- * same formulas.  Required macros: SC, SC_EXP, SC_LOG, FN_RHS, FN_FALLOFF.
+ * same formulas.  Required macros: SC, SC_EXP, SC_LOG, FN_RHS, FN_FALLOFF, FN_LNKF.
  *
  * State y = (T, Y_1..Y_N) at fixed pressure p.  With W-bar the mean molar
  * mass, rho = p W-bar / (R T) and C_k = rho Y_k / W_k:
  *   k_f,j  = exp(ln A_j + b_j ln T - Ea_j / (R T))
+ *            or, for a pressure-dependent (PLOG) reaction with rate expressions
+ *            k_i(T) tabulated at increasing pressures p_i (FN_LNKF):
+ *              ln k_f = ln k_i + (ln p - ln p_i) / (ln p_i+1 - ln p_i) (ln k_i+1 - ln k_i)
+ *            for p_i <= p < p_i+1, and k_1 below p_1, k_last at or above p_last
  *   ln Kc  = -sum_k nu_kj G_k/(RT) + (sum_k nu_kj) ln(p_atm / (R T))
  *   k_r,j  = exp(ln k_f,j - ln Kc,j)
  *   q_j    = m_j (k_f prod_reactants C - k_r prod_products C),
@@ -29,6 +33,21 @@
  *   H/RT = a1 + a2 T/2 + a3 T^2/3 + a4 T^3/4 + a5 T^4/5 + a6/T
  *   S/R  = a1 ln T + a2 T + a3 T^2/2 + a4 T^3/3 + a5 T^4/4 + a7
  */
+
+static SC FN_LNKF(const omech *m, int j, double p, SC T, SC lnT)
+{
+    const int cnt = m->plog_n ? m->plog_n[j] : 0;
+    if (!cnt) return m->lnA[j] + m->b[j] * lnT - m->Ea[j] / (ORC_RU_J * T);
+    const double *t = m->plog + (size_t)32 * j;      /* p_i, A_i, b_i, Ea_i */
+    int i = 0;
+    if (p >= t[4 * (cnt - 1)]) i = cnt - 1;
+    else while (i + 1 < cnt && p >= t[4 * (i + 1)]) ++i;
+    const SC lk = log(t[4 * i + 1]) + t[4 * i + 2] * lnT - t[4 * i + 3] / (ORC_RU_J * T);
+    if (p < t[0] || i == cnt - 1) return lk;         /* outside the table: end entry */
+    const SC lk1 = log(t[4 * i + 5]) + t[4 * i + 6] * lnT - t[4 * i + 7] / (ORC_RU_J * T);
+    const double w = (log(p) - log(t[4 * i])) / (log(t[4 * i + 4]) - log(t[4 * i]));
+    return lk + w * (lk1 - lk);
+}
 
 static SC FN_FALLOFF(const omech *m, int j, SC T, SC lnT, SC kinf, SC M)
 {
@@ -81,7 +100,7 @@ static void FN_RHS(const omech *m, double p, const SC *y, SC *f)
     const SC ln_patm_RT = SC_LOG(ORC_P_ATM / (ORC_RU_ERG * T));
     for (int j = 0; j < R; ++j) {
         const int *rs = m->reac + 2 * j, *ps = m->prod + 3 * j;
-        SC ln_kf = m->lnA[j] + m->b[j] * lnT - m->Ea[j] / (ORC_RU_J * T);
+        SC ln_kf = FN_LNKF(m, j, p, T, lnT);
         SC dG = 0.0;
         SC Pf = 1.0, Pr = 1.0;
         for (int s = 0; s < 2; ++s) if (rs[s] >= 0) { dG -= g_RT[rs[s]]; Pf *= C[rs[s]]; }

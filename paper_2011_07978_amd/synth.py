@@ -57,12 +57,16 @@ class Mechanism:
     name: str = ""
     falloff: np.ndarray = None     # [R] int32 0 none, 1 Lindemann, 2 Troe (third-body reactions)
     fo_params: np.ndarray = None   # [R, 7] A0 (CGS), b0, Ea0 (J/mol), a, T3, T1, T2 (<= 0: absent)
+    plog_count: np.ndarray = None  # [R] int32 0, or 2..8 tabulated pressures (PLOG reactions)
+    plog_params: np.ndarray = None # [R, 8, 4] p_i (dyn/cm^2, increasing), A_i (CGS), b_i, Ea_i (J/mol)
 
     def arrays(self):
         keys = ["elem_mass", "composition", "W", "nasa", "reactants", "products",
                 "A", "b", "Ea", "third_body", "eff_reaction", "eff_species", "eff_value"]
         if self.falloff is not None:
             keys += ["falloff", "fo_params"]
+        if self.plog_count is not None:
+            keys += ["plog_count", "plog_params"]
         return {k: getattr(self, k) for k in keys}
 
     def save(self, path):
@@ -170,7 +174,7 @@ def _balanced_pairs(comp, inert):
 
 def make_mechanism(n_species: int, n_reactions: int, n_elements: int, seed: int,
                    third_body_frac: float = 0.2, name: str = "",
-                   falloff_frac: float = 0.0) -> Mechanism:
+                   falloff_frac: float = 0.0, plog_frac: float = 0.0) -> Mechanism:
     """Seeded synthetic reversible mechanism (see module docstring).
 
     Thermo: a1 ~ U(2.5, 4.5) + (atoms - 1)/2; a2..a5 = u a1 / (8 T_MAX^(m-1)),
@@ -191,6 +195,10 @@ def make_mechanism(n_species: int, n_reactions: int, n_elements: int, seed: int,
     Troe a ~ U(0.2, 0.9), T3 = 10^U(1.5, 3) K, T1 = 10^U(3, 4) K and, for half
     of them, T2 = 10^U(3, 4) K (else absent).  These draws come after all
     others, so a mechanism without fall-off is unchanged by the option.
+    Pressure dependence by tabulation (PLOG; plog_frac of the reactions without
+    a third body): 2 to 5 pressures log-uniform in [0.1, 100] atm, at each an
+    Arrhenius form A 10^U(-1, 1), b + U(-0.3, 0.3), Ea U(0.8, 1.2).  These draws
+    come last.
     """
     rng = _rng(seed)
     T_MAX = 10000.0
@@ -271,11 +279,29 @@ def make_mechanism(n_species: int, n_reactions: int, n_elements: int, seed: int,
                 fo_params[j, 4] = 10.0 ** rng.uniform(1.5, 3.0)
                 fo_params[j, 5] = 10.0 ** rng.uniform(3.0, 4.0)
                 fo_params[j, 6] = 10.0 ** rng.uniform(3.0, 4.0) if rng.uniform() < 0.5 else 0.0
+    plog_count = plog_params = None
+    if plog_frac > 0.0:
+        free = np.nonzero(third == 0)[0]
+        pick = np.sort(rng.choice(free, size=int(round(plog_frac * free.size)), replace=False))
+        plog_count = np.zeros(R, dtype=np.int32)
+        plog_params = np.zeros((R, 8, 4))
+        for j in pick:
+            cnt = int(rng.integers(2, 6))
+            while True:
+                e = np.sort(rng.uniform(-1.0, 2.0, size=cnt))
+                if np.all(np.diff(e) > 0.05):
+                    break
+            plog_count[j] = cnt
+            plog_params[j, :cnt, 0] = P_ATM * 10.0 ** e
+            plog_params[j, :cnt, 1] = A[j] * 10.0 ** rng.uniform(-1.0, 1.0, size=cnt)
+            plog_params[j, :cnt, 2] = b[j] + rng.uniform(-0.3, 0.3, size=cnt)
+            plog_params[j, :cnt, 3] = Ea[j] * rng.uniform(0.8, 1.2, size=cnt)
     return Mechanism(n_elements, n_species, R, elem_mass, comp, W, nasa,
                      reactants, products, A, b, Ea, third,
                      np.array(eff_r, dtype=np.int32), np.array(eff_s, dtype=np.int32),
                      np.array(eff_v, dtype=np.float64), seed=seed, name=name,
-                     falloff=falloff, fo_params=fo_params)
+                     falloff=falloff, fo_params=fo_params,
+                     plog_count=plog_count, plog_params=plog_params)
 
 
 # ----------------------------------------------------------------------------
@@ -294,6 +320,12 @@ MECH_SPECS = {
                      falloff_frac=0.5),
     "mech64fo": dict(n_species=64, n_reactions=400, n_elements=4, seed=7, third_body_frac=0.2,
                      falloff_frac=0.5),
+    # tabulated pressure dependence (PLOG) on a fifth of the other reactions,
+    # next to fall-off on half of the third-body reactions
+    "mech53pl": dict(n_species=53, n_reactions=325, n_elements=4, seed=8, third_body_frac=0.2,
+                     falloff_frac=0.5, plog_frac=0.2),
+    "mech64pl": dict(n_species=64, n_reactions=400, n_elements=4, seed=9, third_body_frac=0.2,
+                     falloff_frac=0.5, plog_frac=0.2),
 }
 
 _MECH_CACHE = {}
