@@ -320,11 +320,12 @@ MECH_SPECS = {
                      falloff_frac=0.5),
     "mech64fo": dict(n_species=64, n_reactions=400, n_elements=4, seed=7, third_body_frac=0.2,
                      falloff_frac=0.5),
-    # tabulated pressure dependence (PLOG) on a fifth of the other reactions,
-    # next to fall-off on half of the third-body reactions
-    "mech53pl": dict(n_species=53, n_reactions=325, n_elements=4, seed=8, third_body_frac=0.2,
+    # the two fall-off mechanisms with tabulated pressure dependence (PLOG) on
+    # a fifth of the reactions without a third body (drawn last, so everything
+    # else equals mech53fo / mech64fo)
+    "mech53pl": dict(n_species=53, n_reactions=325, n_elements=4, seed=6, third_body_frac=0.2,
                      falloff_frac=0.5, plog_frac=0.2),
-    "mech64pl": dict(n_species=64, n_reactions=400, n_elements=4, seed=9, third_body_frac=0.2,
+    "mech64pl": dict(n_species=64, n_reactions=400, n_elements=4, seed=7, third_body_frac=0.2,
                      falloff_frac=0.5, plog_frac=0.2),
 }
 
