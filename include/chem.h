@@ -91,7 +91,15 @@ typedef struct chem_ctx chem_ctx;
  * or log10 F = log10 Fcent / (1 + f1^2), f1 = x / (n - 0.14 x),
  * x = log10 Pr - 0.4 - 0.67 log10 Fcent, n = 0.75 - 1.27 log10 Fcent,
  * Fcent = (1 - a) exp(-T/T3) + a exp(-T/T1) + exp(-T2/T) (Troe).  The
- * reverse rate carries the same G. */
+ * reverse rate carries the same G.
+ * Reactions with tabulated pressure dependence (PLOG; plog_count[j] = 2..8,
+ * reactions without a third body) ignore A, b, Ea: plog_params[32j + 4i ..]
+ * = p_i (dyn/cm^2, strictly increasing), A_i, b_i, Ea_i (J/mol) give rate
+ * expressions k_i(T) at the pressures p_i, and at the cell's pressure p,
+ * ln k = ln k_i + (ln p - ln p_i) / (ln p_i+1 - ln p_i) (ln k_i+1 - ln k_i)
+ * for p_i <= p < p_i+1, k_1 below p_1 and k_last from p_last on (the usual
+ * PLOG form of kinetics input; the paper's chemistry model, Sec. 2.1, takes
+ * its rates from such input). */
 typedef struct {
     int32_t n_elements, n_species, n_reactions;
     const double *elem_mass;     /* [E] g/mol */
@@ -111,6 +119,8 @@ typedef struct {
     const double *eff_value;     /* [n_eff] efficiency alpha */
     const int32_t *falloff;      /* [R] nullable: 0 none, 1 Lindemann, 2 Troe */
     const double *falloff_params;/* [R*7] nullable (required with falloff) */
+    const int32_t *plog_count;   /* [R] nullable: 0, or 2..8 tabulated pressures */
+    const double *plog_params;   /* [R*32] nullable (required with plog_count) */
 } chem_mech_desc;
 
 typedef struct {

@@ -30,7 +30,7 @@ class MechDesc(C.Structure):
                 ("reactants", _i32), ("products", _i32), ("A", _d), ("b", _d), ("Ea", _d),
                 ("third_body", _i32), ("n_eff", C.c_int32), ("eff_reaction", _i32),
                 ("eff_species", _i32), ("eff_value", _d), ("falloff", _i32),
-                ("falloff_params", _d)]
+                ("falloff_params", _d), ("plog_count", _i32), ("plog_params", _d)]
 
 
 class Options(C.Structure):
@@ -242,12 +242,18 @@ class Chem:
         fo_p = getattr(mech, "fo_params", None)
         if fo_t is not None:
             k += [_np(fo_t, np.int32), _np(fo_p, np.float64)]
+        pl_n = getattr(mech, "plog_count", None)
+        pl = []
+        if pl_n is not None:
+            pl = [_np(pl_n, np.int32), _np(mech.plog_params, np.float64)]
+            k += pl
         d = MechDesc(int(mech.n_elements), int(mech.n_species), int(mech.n_reactions),
                      P(k[0], _d), P(k[1], _i32), P(k[2], _d), P(k[3], _d), P(k[4], _i32),
                      P(k[5], _i32), P(k[6], _d), P(k[7], _d), P(k[8], _d), P(k[9], _i32),
                      int(k[12].size), P(k[10], _i32), P(k[11], _i32), P(k[12], _d),
                      P(k[13], _i32) if fo_t is not None else None,
-                     P(k[14], _d) if fo_t is not None else None)
+                     P(k[14], _d) if fo_t is not None else None,
+                     P(pl[0], _i32) if pl else None, P(pl[1], _d) if pl else None)
         self._check(self.L.chem_set_mechanism(self.h, C.byref(d)), "chem_set_mechanism")
         self.mech = mech
         return self

@@ -466,6 +466,31 @@ int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
             any_fo = true;
         }
     }
+    // third-body codes of reactions with efficiency lists must fit TB_CODE
+    {
+        int lists = 0;
+        for (int j = 0; j < R; ++j) lists += eff[j].size() > 3;
+        if (TB_LIST0 + lists - 1 > TB_CODE)
+            return fail(c, CHEM_E_BAD_MECHANISM, "too many third-body efficiency lists (%d)", lists);
+    }
+    // PLOG tables: reactions without a third body, 2..8 entries, strictly
+    // increasing positive pressures, A_i > 0, finite parameters
+    bool any_plog = false;
+    if (m->plog_count) {
+        if (!m->plog_params) return fail(c, CHEM_E_BAD_MECHANISM, "plog_count without plog_params");
+        for (int j = 0; j < R; ++j) {
+            const int cnt = m->plog_count[j];
+            if (cnt == 0) continue;
+            bool ok = cnt >= 2 && cnt <= 8 && !is_tb[j];
+            const double *t = m->plog_params + 32 * (size_t)j;
+            for (int i = 0; ok && i < cnt; ++i) {
+                for (int q = 0; q < 4; ++q) ok = ok && isfinite(t[4 * i + q]);
+                ok = ok && t[4 * i] > 0.0 && t[4 * i + 1] > 0.0 && (i == 0 || t[4 * i] > t[4 * i - 4]);
+            }
+            if (!ok) return fail(c, CHEM_E_BAD_MECHANISM, "reaction %d: bad PLOG table", j);
+            any_plog = true;
+        }
+    }
 
     HIPCHK(c, hipSetDevice(c->device));
     free_mech(c);
@@ -529,6 +554,7 @@ int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
         q.idx[0] = r0 | (r1 << 16);
         q.idx[1] = p0 | (p1 << 16);
         if (any_fo && m->falloff[j]) tb |= TB_FALLOFF;
+        if (any_plog && m->plog_count[j]) tb |= TB_PLOG;
         q.idx[2] = p2 | (tb << 16);
         q.idx[3] = (snu + 8) | (es[0] << 8) | (es[1] << 16) | (es[2] << 24);
         q.lnA = log(m->A[j]);
@@ -548,9 +574,26 @@ int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
             d[3] = f[3]; d[4] = f[4]; d[5] = f[5]; d[6] = f[6];
             d[7] = (double)m->falloff[j];
         }
+    // PLOG tables by reaction slot
+    std::vector<double> pl(any_plog ? (size_t)R * PLOG_STRIDE : 1, 0.0);
+    if (any_plog)
+        for (int i = 0; i < R; ++i) {
+            const int j = ord[i].src;
+            const int cnt = m->plog_count[j];
+            if (!cnt) continue;
+            const double *t = m->plog_params + 32 * (size_t)j;
+            double *d = &pl[(size_t)i * PLOG_STRIDE];
+            d[0] = (double)cnt;
+            for (int e = 0; e < cnt; ++e) {
+                d[1 + 4 * e] = log(t[4 * e]);
+                d[2 + 4 * e] = log(t[4 * e + 1]);
+                d[3 + 4 * e] = t[4 * e + 2];
+                d[4 + 4 * e] = t[4 * e + 3] / RU_J;
+            }
+        }
     MechDev &M = c->M;
     M = MechDev{};
-    M.has_fo = any_fo ? 1 : 0;
+    M.has_fo = (any_fo || any_plog) ? 1 : 0;
     M.N = N; M.R = R; M.n = N + 1;
     M.ldj = (M.n % 2) ? M.n : M.n + 1;
     int rc;
@@ -558,7 +601,7 @@ int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
         (rc = upload(c, invW, &M.invW)) || (rc = upload(c, spc, &M.spc)) ||
         (rc = upload(c, rxn, &M.rxn)) || (rc = upload(c, tb_ptr, &M.tb_ptr)) ||
         (rc = upload(c, eff_sp, &M.eff_sp)) || (rc = upload(c, eff_am1, &M.eff_am1)) ||
-        (rc = upload(c, fo, &M.fo))) {
+        (rc = upload(c, fo, &M.fo)) || (rc = upload(c, pl, &M.plog))) {
         free_mech(c);
         return rc;
     }

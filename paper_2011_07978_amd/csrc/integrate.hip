@@ -135,6 +135,7 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
     // their reactant and product slots (LDS float atomics; missing slots hit
     // the sentinel entry N)
     const double ln_patm_RT = log(P_ATM / (RU_ERG * T));
+    const double lnp = FO ? log(p) : 0.0;
     const RxnRec *rxn = LT ? reinterpret_cast<const RxnRec *>(lds_all + N * SPC_STRIDE)
                            : (const RxnRec *)gbl(M.rxn);
     auto reaction = [&](const int j, const bool valid) {
@@ -149,8 +150,9 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
         const int es2 = (int)((unsigned)ix3 >> 24);
         const double Cr0 = Cl[r0], Cr1 = Cl[r1], Cp0 = Cl[p0], Cp1 = Cl[p1], Cp2 = Cl[p2];
         const double dG = -gl[r0] - gl[r1] + gl[p0] + gl[p1] + gl[p2];
-        const double bj = rec.b, EaRj = rec.EaR;
-        const double ln_kf = rec.lnA + bj * lnT - EaRj * invT;
+        double lnAj = rec.lnA, bj = rec.b, EaRj = rec.EaR;
+        if (FO && (tbw & TB_PLOG)) plog_arrhenius(M.plog + (size_t)j * PLOG_STRIDE, lnp, lnAj, bj, EaRj);
+        const double ln_kf = lnAj + bj * lnT - EaRj * invT;
         const double ln_Kc = -dG + snu * ln_patm_RT;
         const double kf = exp(ln_kf);
         const double kr = exp(ln_kf - ln_Kc);

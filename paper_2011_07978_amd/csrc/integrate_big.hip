@@ -160,6 +160,7 @@ __device__ double rhs_big(const MechDev *__restrict__ Mp, const double p, const 
     __syncthreads();
 
     const double ln_patm_RT = log(P_ATM / (RU_ERG * T));
+    const double lnp = log(p);
     const auto *rxn = gbl(M.rxn);
     double *Cl = L.C, *gl = L.g, *hl = L.hh, *wl = L.w, *Jl = L.A, *tbl = L.tb;
     // Reactions j0 + tid are evaluated by all four wavefronts at once; their
@@ -180,8 +181,10 @@ __device__ double rhs_big(const MechDev *__restrict__ Mp, const double p, const 
         const int es2 = (int)((unsigned)ix3 >> 24);
         const double Cr0 = Cl[r0], Cr1 = Cl[r1], Cp0 = Cl[p0], Cp1 = Cl[p1], Cp2 = Cl[p2];
         const double dG = -gl[r0] - gl[r1] + gl[p0] + gl[p1] + gl[p2];
-        const double bj = rec.b, EaRj = rec.EaR;
-        const double ln_kf = rec.lnA + bj * lnT - EaRj * invT;
+        double lnAj = rec.lnA, bj = rec.b, EaRj = rec.EaR;
+        if (tbw & TB_PLOG)
+            plog_arrhenius(M.plog + (size_t)(valid ? j0 + tid : R - 1) * PLOG_STRIDE, lnp, lnAj, bj, EaRj);
+        const double ln_kf = lnAj + bj * lnT - EaRj * invT;
         const double ln_Kc = -dG + snu * ln_patm_RT;
         const double kf = exp(ln_kf);
         const double kr = exp(ln_kf - ln_Kc);

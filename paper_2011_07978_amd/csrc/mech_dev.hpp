@@ -18,7 +18,8 @@ constexpr int SPC_STRIDE = 18;
 // Reaction record (64 bytes).  idx[0] = r0 | r1 << 16, idx[1] = p0 | p1 << 16,
 // idx[2] = p2 | tb << 16, idx[3] = (sum_nu + 8) | es0 << 8 | es1 << 16 | es2 << 24.
 // Bit 15 of tb (TB_FALLOFF) marks a fall-off reaction, whose parameters are
-// in MechDev::fo at the reaction's slot.
+// in MechDev::fo at the reaction's slot; bit 14 (TB_PLOG) a reaction with
+// tabulated pressure dependence, whose table is in MechDev::plog.
 // Missing slots hold the sentinel species N.  tb = 0: no third body;
 // tb = 1: third body with up to three listed efficiencies stored inline
 // (alpha - 1 in eff[], species es0..es2, unused ones eff = 0, es = N);
@@ -29,7 +30,7 @@ struct RxnRec {
     int idx[4];
 };
 constexpr int TB_NONE = 0, TB_INLINE = 1, TB_LIST0 = 2;
-constexpr int TB_FALLOFF = 0x8000, TB_CODE = 0x7fff;
+constexpr int TB_FALLOFF = 0x8000, TB_PLOG = 0x4000, TB_CODE = 0x3fff;
 
 // Fall-off parameters of one reaction slot (8 doubles): ln A0, b0, Ea0 / R,
 // Troe a, T3, T1, T2 (<= 0: no T2 term), form (1 Lindemann, 2 Troe).
@@ -74,6 +75,34 @@ __device__ __forceinline__ void falloff_eval(const double *__restrict__ f, doubl
     dlnGdT = (inv1p + S) * (dlnk0 - dlnkinf) + dlnF_dT;
 }
 
+// Tabulated pressure dependence (PLOG) of one reaction slot (PLOG_STRIDE
+// doubles): the number of entries (2..8), then per entry ln p_i (p in
+// dyn/cm^2, increasing), ln A_i, b_i, Ea_i / R.
+constexpr int PLOG_STRIDE = 33;
+
+// Arrhenius parameters of a PLOG reaction at the cell's pressure: ln k is
+// linear in ln p between the two tabulated pressures around p, and equals the
+// end entry's outside the table.  At a fixed p this is the Arrhenius form
+// whose ln A, b and Ea/R are interpolated with the same weight.
+__device__ __forceinline__ void plog_arrhenius(const double *__restrict__ t, double lnp, double &lnA,
+                                               double &b, double &EaR) {
+    const int cnt = (int)t[0];
+    const double *e = t + 1;
+    int i = 0;
+    while (i + 2 < cnt && lnp >= e[4 * (i + 1)]) ++i;
+    const double *lo = e + 4 * i, *hi = lo + 4;
+    const double w = (lnp - lo[0]) / (hi[0] - lo[0]);
+    if (w <= 0.0) {
+        lnA = lo[1]; b = lo[2]; EaR = lo[3];
+    } else if (w >= 1.0) {
+        lnA = hi[1]; b = hi[2]; EaR = hi[3];
+    } else {
+        lnA = lo[1] + w * (hi[1] - lo[1]);
+        b = lo[2] + w * (hi[2] - lo[2]);
+        EaR = lo[3] + w * (hi[3] - lo[3]);
+    }
+}
+
 // Loads through this cast are global-memory loads (not flat), so they do not
 // share a wait counter with LDS traffic.
 template <class T>
@@ -93,7 +122,8 @@ struct MechDev {
     const int *eff_sp;
     const double *eff_am1;  // alpha - 1
     const double *fo;       // [R][FO_STRIDE] fall-off parameters by reaction slot
-    int has_fo;             // any fall-off reaction
+    const double *plog;     // [R][PLOG_STRIDE] PLOG tables by reaction slot
+    int has_fo;             // any fall-off or PLOG reaction
     // LDS layout (offsets in doubles)
     int off_J, off_q, off_C, off_g, off_h, off_e, off_cp, off_tb, off_sv, lds_doubles;
 };
