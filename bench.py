@@ -288,8 +288,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="surrogate",
-                    choices=["small", "flame", "flame_shuffled", "flame_hot_last", "mapped", "large",
-                             "surrogate", "unit", "mapping-study"],
+                    choices=["small", "flame", "flame_shuffled", "flame_hot_last", "flame_falloff",
+                             "flame_plog", "mapped", "large", "surrogate", "unit", "mapping-study"],
                     help="unit: the load-balancing benchmark of Sec. 3 (layouts C1-C4); "
                          "mapping-study: mapped vs unmapped error over Z_tol and the T criterion")
     ap.add_argument("--unit-problems", type=int, default=100,

@@ -480,6 +480,9 @@ WORKLOADS = {
     "flame": dict(mech="mech53", field=lambda n=65536: field_bimodal("mech53", n, 102)),
     "flame_shuffled": dict(mech="mech53", field=lambda n=65536: field_bimodal("mech53", n, 102, shuffle=True)),
     "flame_hot_last": dict(mech="mech53", field=lambda n=65536: field_bimodal("mech53", n, 102, hot_last=True)),
+    # the same field recipe with richer kinetics: fall-off, and fall-off plus PLOG
+    "flame_falloff": dict(mech="mech53fo", field=lambda n=65536: field_bimodal("mech53fo", n, 102)),
+    "flame_plog": dict(mech="mech53pl", field=lambda n=65536: field_bimodal("mech53pl", n, 102)),
     "mapped": dict(mech="mech53", field=lambda n=262144: field_mapped(n, 103)),
     "large": dict(mech="mech130", field=lambda n=131072: field_bimodal("mech130", n, 104, dt=2e-6)),
     "surrogate": dict(mech="mech53", field=lambda n=1048576: field_mapped(n, 105, n_steps=1)),
