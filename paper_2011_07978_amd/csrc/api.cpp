@@ -318,20 +318,19 @@ static int setup_surrogate(chem_ctx *c) {
 // instruction that hit the same species are serialised.  Reactions are placed
 // greedily, busiest first, into the 64-wide group and slot permutation that
 // adds the least to the per-group, per-slot species counts.  Present species
-// stay in the leading slots (missing ones are skipped by the kernels).  Sums
-// change only by rounding order.
+// stay in the leading slots (missing ones are skipped by the kernels).
+// Reactions of one kind (plain, fall-off, PLOG) are placed in slots of their
+// own, kind after kind, so that the extra code of a fall-off or PLOG rate runs
+// in the few groups that hold such reactions instead of diverging in every
+// group.  Sums change only by rounding order.
 struct RxnSlots {
     int src;      // mechanism index
     int sp[5];    // r0 r1 p0 p1 p2, -1 missing
 };
-static std::vector<RxnSlots> order_reactions(int N, int R, const int *rea, const int *pro) {
-    std::vector<int> freq(N, 0);
-    for (int j = 0; j < R; ++j) {
-        for (int s = 0; s < 2; ++s) if (rea[2 * j + s] >= 0) ++freq[rea[2 * j + s]];
-        for (int s = 0; s < 3; ++s) if (pro[3 * j + s] >= 0) ++freq[pro[3 * j + s]];
-    }
-    std::vector<int> byw(R);
-    for (int j = 0; j < R; ++j) byw[j] = j;
+static void order_group(int N, const std::vector<int> &subset, const std::vector<int> &freq,
+                        const int *rea, const int *pro, std::vector<RxnSlots> &out) {
+    const int R = (int)subset.size();
+    std::vector<int> byw(subset);
     auto weight = [&](int j) {
         int w = 0;
         for (int s = 0; s < 2; ++s) if (rea[2 * j + s] >= 0) w += freq[rea[2 * j + s]];
@@ -379,11 +378,25 @@ static std::vector<RxnSlots> order_reactions(int N, int R, const int *rea, const
         ++fill[pick_b];
         blocks[pick_b].push_back(pick);
     }
-    std::vector<RxnSlots> out;
-    out.reserve(R);
     for (auto &bl : blocks) {
         std::sort(bl.begin(), bl.end(), [](const RxnSlots &a, const RxnSlots &b) { return a.src < b.src; });
         out.insert(out.end(), bl.begin(), bl.end());
+    }
+}
+// kind[j]: 0 plain, 1 fall-off, 2 PLOG
+static std::vector<RxnSlots> order_reactions(int N, int R, const int *rea, const int *pro,
+                                             const std::vector<int> &kind) {
+    std::vector<int> freq(N, 0);
+    for (int j = 0; j < R; ++j) {
+        for (int s = 0; s < 2; ++s) if (rea[2 * j + s] >= 0) ++freq[rea[2 * j + s]];
+        for (int s = 0; s < 3; ++s) if (pro[3 * j + s] >= 0) ++freq[pro[3 * j + s]];
+    }
+    std::vector<RxnSlots> out;
+    out.reserve(R);
+    for (int k = 0; k < 3; ++k) {
+        std::vector<int> subset;
+        for (int j = 0; j < R; ++j) if (kind[j] == k) subset.push_back(j);
+        if (!subset.empty()) order_group(N, subset, freq, rea, pro, out);
     }
     return out;
 }
@@ -526,7 +539,10 @@ int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
     std::vector<RxnRec> rxn(R);
     std::vector<int> tb_ptr(1, 0), eff_sp;
     std::vector<double> eff_am1;
-    const std::vector<RxnSlots> ord = order_reactions(N, R, m->reactants, m->products);
+    std::vector<int> kind(R, 0);
+    for (int j = 0; j < R; ++j)
+        kind[j] = (any_fo && m->falloff[j]) ? 1 : (any_plog && m->plog_count[j]) ? 2 : 0;
+    const std::vector<RxnSlots> ord = order_reactions(N, R, m->reactants, m->products, kind);
     for (int i = 0; i < R; ++i) {
         const int j = ord[i].src;
         auto sl = [&](int s) { return ord[i].sp[s] < 0 ? N : ord[i].sp[s]; };
