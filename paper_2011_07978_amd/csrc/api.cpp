@@ -319,10 +319,11 @@ static int setup_surrogate(chem_ctx *c) {
 // greedily, busiest first, into the 64-wide group and slot permutation that
 // adds the least to the per-group, per-slot species counts.  Present species
 // stay in the leading slots (missing ones are skipped by the kernels).
-// Reactions of one kind (plain, fall-off, PLOG) are placed in slots of their
-// own, kind after kind, so that the extra code of a fall-off or PLOG rate runs
-// in the few groups that hold such reactions instead of diverging in every
-// group.  Sums change only by rounding order.
+// Reactions of one kind are placed in slots of their own, kind after kind
+// (plain, PLOG, third-body, fall-off), so that the extra code of a PLOG rate,
+// a third body (its Jacobian terms) or a fall-off rate runs in the few groups
+// that hold such reactions instead of diverging in every group.  Sums change
+// only by rounding order.
 struct RxnSlots {
     int src;      // mechanism index
     int sp[5];    // r0 r1 p0 p1 p2, -1 missing
@@ -383,7 +384,7 @@ static void order_group(int N, const std::vector<int> &subset, const std::vector
         out.insert(out.end(), bl.begin(), bl.end());
     }
 }
-// kind[j]: 0 plain, 1 fall-off, 2 PLOG
+// kind[j]: 0 plain, 1 PLOG, 2 third-body, 3 fall-off
 static std::vector<RxnSlots> order_reactions(int N, int R, const int *rea, const int *pro,
                                              const std::vector<int> &kind) {
     std::vector<int> freq(N, 0);
@@ -393,7 +394,7 @@ static std::vector<RxnSlots> order_reactions(int N, int R, const int *rea, const
     }
     std::vector<RxnSlots> out;
     out.reserve(R);
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
         std::vector<int> subset;
         for (int j = 0; j < R; ++j) if (kind[j] == k) subset.push_back(j);
         if (!subset.empty()) order_group(N, subset, freq, rea, pro, out);
@@ -541,7 +542,7 @@ int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
     std::vector<double> eff_am1;
     std::vector<int> kind(R, 0);
     for (int j = 0; j < R; ++j)
-        kind[j] = (any_fo && m->falloff[j]) ? 1 : (any_plog && m->plog_count[j]) ? 2 : 0;
+        kind[j] = (any_fo && m->falloff[j]) ? 3 : is_tb[j] ? 2 : (any_plog && m->plog_count[j]) ? 1 : 0;
     const std::vector<RxnSlots> ord = order_reactions(N, R, m->reactants, m->products, kind);
     for (int i = 0; i < R; ++i) {
         const int j = ord[i].src;
