@@ -427,7 +427,7 @@ def main():
     traffic = None
     plain_kinetics = getattr(mech, "falloff", None) is None and getattr(mech, "plog_count", None) is None
     if kname == "k_integrate_queue" and mech.n_species == 53 and plain_kinetics:
-        traffic = 8631.0 * float(np.mean([s["cells_integrated"] for s in st_h]))
+        traffic = 8585.0 * float(np.mean([s["cells_integrated"] for s in st_h]))
     roof = dict(bound="alu", achieved=achieved, peak=accounting.FP64_VECTOR_PEAK_TFLOPS,
                 unit="TFLOP/s", frac=achieved / accounting.FP64_VECTOR_PEAK_TFLOPS, traffic=traffic,
                 traffic_unit="bytes per launch" if traffic else None,
