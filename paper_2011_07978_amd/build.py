@@ -10,7 +10,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libchem.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.cpp", "balance.cpp", "integrate.hip", "integrate_big.hip", "map_queue.hip", "mlp.hip"]
+SOURCES = ["api.cpp", "balance.cpp", "integrate.hip", "integrate_fo.hip", "integrate_big.hip",
+           "map_queue.hip", "mlp.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
           # packed FP32 instructions are kept out of every kernel
@@ -31,7 +32,7 @@ def _compile(src, verbose):
     return obj
 
 
-def build(verbose=False, jobs=4):
+def build(verbose=False, jobs=7):
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))

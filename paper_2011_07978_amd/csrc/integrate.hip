@@ -28,14 +28,14 @@ namespace chem {
 // Rodas4, Hairer & Wanner, Solving ODEs II, Sec. IV.7, transformed form:
 // (I/(gamma h) - J) u_i = f(y + sum_j a_ij u_j) + sum_j (c_ij / h) u_j.
 // Row 5 of A is the stage-6 input (a_5j, then 1 for u_5).
-__constant__ double kRodasA[6][6] = {
+static __constant__ double kRodasA[6][6] = {
     {0, 0, 0, 0, 0, 0},
     {1.544, 0, 0, 0, 0, 0},
     {0.9466785280815826, 0.2557011698983284, 0, 0, 0, 0},
     {3.314825187068521, 2.896124015972201, 0.9986419139977817, 0, 0, 0},
     {1.221224509226641, 6.019134481288629, 12.53708332932087, -0.6878860361058950, 0, 0},
     {1.221224509226641, 6.019134481288629, 12.53708332932087, -0.6878860361058950, 1.0, 0}};
-__constant__ double kRodasC[6][6] = {
+static __constant__ double kRodasC[6][6] = {
     {0, 0, 0, 0, 0, 0},
     {-5.6688, 0, 0, 0, 0, 0},
     {-2.430093356833875, -0.2063599157091915, 0, 0, 0, 0},
@@ -721,6 +721,20 @@ __global__ __launch_bounds__(64) void k_rodas_step(const MechDev *__restrict__ M
 // -----------------------------------------------------------------------------
 #define CHEM_NP_LIST(X) X(12) X(16) X(24) X(32) X(40) X(48) X(54) X(56) X(64)
 
+// The host side is built as two translation units that compile in parallel:
+// part 0 (this file) instantiates the kernels for mechanisms with plain
+// kinetics and holds the dispatch; part 1 (integrate_fo.hip, which includes
+// this file) instantiates the fall-off / PLOG kernels and the single-call
+// test kernels.
+#ifndef CHEM_INTEGRATE_PART
+#define CHEM_INTEGRATE_PART 0
+#endif
+
+int wave_kernel_wpb(const MechDev &M);
+hipError_t launch_integrate_fo(int NP, const MechDev &M, const MechDev *Md, const IntParams &P,
+                               int schedule, int grid, hipStream_t s);
+
+#if CHEM_INTEGRATE_PART == 0
 int pick_np(int n) {
 #define PICK(v) if (n <= v) return v;
     CHEM_NP_LIST(PICK)
@@ -736,6 +750,7 @@ int wave_kernel_wpb(const MechDev &M) {
         if (sizeof(double) * ((size_t)table_doubles(M) + (size_t)w * M.lds_doubles) <= kLdsCap) return w;
     return 0;
 }
+#endif
 static size_t lds_bytes(const MechDev &M, int wpb) {
     return sizeof(double) * ((size_t)table_doubles(M) + (size_t)wpb * M.lds_doubles);
 }
@@ -762,11 +777,12 @@ static hipError_t launch_integrate_np(const MechDev &M, const MechDev *Md, const
     return hipGetLastError();
 }
 
+#if CHEM_INTEGRATE_PART == 0
 hipError_t launch_integrate(int NP, const MechDev &M, const MechDev *Md, const IntParams &P,
                             int schedule, int grid, hipStream_t s) {
+    if (M.has_fo) return launch_integrate_fo(NP, M, Md, P, schedule, grid, s);
     switch (NP) {
-#define CASE(v) case v: return M.has_fo ? launch_integrate_np<v, true>(M, Md, P, schedule, grid, s) \
-                                 : launch_integrate_np<v, false>(M, Md, P, schedule, grid, s);
+#define CASE(v) case v: return launch_integrate_np<v, false>(M, Md, P, schedule, grid, s);
         CHEM_NP_LIST(CASE)
 #undef CASE
     }
@@ -790,6 +806,17 @@ int queue_occupancy(int NP, const MechDev &M) {
 #undef CASE
     }
     return blocks;
+}
+
+#else
+hipError_t launch_integrate_fo(int NP, const MechDev &M, const MechDev *Md, const IntParams &P,
+                               int schedule, int grid, hipStream_t s) {
+    switch (NP) {
+#define CASE(v) case v: return launch_integrate_np<v, true>(M, Md, P, schedule, grid, s);
+        CHEM_NP_LIST(CASE)
+#undef CASE
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_eval_rhs_jac(int NP, const MechDev &M, const MechDev *Md, const IntParams &P,
@@ -823,5 +850,6 @@ hipError_t launch_rodas_step(int NP, const MechDev &M, const MechDev *Md, const 
     }
     return hipErrorInvalidValue;
 }
+#endif
 
 }  // namespace chem
