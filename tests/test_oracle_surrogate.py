@@ -157,3 +157,189 @@ def test_surrogate_cell_gate_and_conservation():
     P2[base + 5 * IN: base + 6 * IN] = 0.0      # xmax: empty box
     ok, T2, Y2 = oracle.surrogate_cell(o, P2, f.p[i], T, Y, 1e-6, tau_T=1e9, y_min=-1.0)
     assert not ok and T2 == T and np.array_equal(Y2, Y)
+
+
+# --------------------------------------------------- closed-form forward pins
+# Standard normal distribution function at 1 and 2 (textbook values): the
+# erf-form GELU is z Phi(z), so GELU(1) = Phi(1) and GELU(2) = 2 Phi(2); for
+# |z| >= 9 the tail is below FP64 resolution, GELU(z) = z (z > 0) or -0 (z < 0).
+PHI1 = 0.8413447460685429
+PHI2 = 0.9772498680518208
+# the same values rounded to bfloat16 by hand (8 significant bits):
+# Phi(1) = 215.38 / 256 -> 215 / 256; 2 Phi(2) = 250.18 / 128 -> 250 / 128
+PHI1_BF16 = 215.0 / 256.0
+TWO_PHI2_BF16 = 250.0 / 128.0
+
+
+def blank_params(nfeat=56):
+    """Every weight and bias zero; identity normalisation; an unbounded box."""
+    P = np.zeros(oracle.mlp_param_count(), np.float32)
+    base = P.size - 6 * IN
+    P[base + IN: base + 2 * IN] = 1.0            # sd_x
+    P[base + 3 * IN: base + 4 * IN] = 1.0        # sd_o
+    P[base + 4 * IN: base + 5 * IN] = -1e30      # xmin
+    P[base + 5 * IN: base + 6 * IN] = 1e30       # xmax
+    return P
+
+
+def layer_views(P):
+    """Writable views W_l [out x in], b_l [out] into the blob."""
+    out, o = [], 0
+    for l in range(5):
+        ni, no = DIMS[l], DIMS[l + 1]
+        W = P[o:o + no * ni].reshape(no, ni)
+        o += no * ni
+        b = P[o:o + no]
+        o += no
+        out.append((W, b))
+    return out, P[o:].reshape(6, IN)
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_forward_zero_hidden_weights_is_output_layer_of_gelu_bias(bf16):
+    """W_1..W_4 = 0: every hidden layer is GELU of its bias alone, so the
+    output is W_5 GELU(b_4) + b_5 whatever b_1..b_3 are.  b_4 holds 0, 40,
+    -40, 1 and 2, whose GELU values are known without evaluating erf."""
+    P = blank_params()
+    L, _ = layer_views(P)
+    rng = np.random.default_rng(11)
+    for l in range(3):
+        L[l][1][:] = rng.standard_normal(HID).astype(np.float32)   # ignored: W_{l+1} = 0
+    b4 = L[3][1]
+    b4[:] = 0.0
+    b4[3], b4[7], b4[11], b4[20] = 40.0, -40.0, 1.0, 2.0
+    g = {3: 40.0, 11: PHI1_BF16 if bf16 else PHI1, 20: TWO_PHI2_BF16 if bf16 else 2 * PHI2}
+    W5, b5 = L[4]
+    # weights and biases that bfloat16 represents exactly (k / 8, |k| <= 64)
+    W5[:, :] = rng.integers(-64, 65, W5.shape).astype(np.float32) / 8.0
+    b5[:] = rng.integers(-64, 65, OUT).astype(np.float32) / 8.0
+    X = np.zeros((3, IN))
+    X[:, :56] = rng.standard_normal((3, 56))
+    out = oracle.mlp_forward(P, X, 56, bf16_emulation=bf16)
+    want = b5.astype(np.float64).copy()
+    for i, gi in g.items():
+        want += W5[:, i].astype(np.float64) * gi
+    for r in range(3):
+        np.testing.assert_allclose(out[r], want, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_forward_one_hot_through_identity_layers(bf16):
+    """Normalisation (x - mu) / sd maps the raw one-hot value 3 of feature j
+    (mu 1, sd 2) to 1; identity first layer: GELU(1) = Phi(1) on unit j, 0
+    elsewhere (GELU(0) = 0); second layer 16 I lifts it to 16 Phi(1) > 9,
+    where GELU is the identity, so layers three and four and the identity
+    output layer pass it through: out = 16 Phi(1) e_j."""
+    nfeat = 56
+    P = blank_params(nfeat)
+    L, nb = layer_views(P)
+    L[0][0][:IN, :IN] = np.eye(IN, dtype=np.float32)
+    L[1][0][:, :] = 16.0 * np.eye(HID, dtype=np.float32)
+    L[2][0][:, :] = np.eye(HID, dtype=np.float32)
+    L[3][0][:, :] = np.eye(HID, dtype=np.float32)
+    L[4][0][:, :IN] = np.eye(OUT, dtype=np.float32)
+    for j in (0, 17, nfeat - 1):
+        nb[0][:] = 0.0
+        nb[1][:] = 1.0
+        nb[0][j], nb[1][j] = 1.0, 2.0
+        X = np.zeros((1, IN))
+        X[0, j] = 3.0
+        out = oracle.mlp_forward(P, X, nfeat, bf16_emulation=bf16)[0]
+        want = np.zeros(OUT)
+        want[j] = 16.0 * (PHI1_BF16 if bf16 else PHI1)
+        np.testing.assert_allclose(out, want, rtol=1e-15, atol=0)
+    # features past nfeat never enter, whatever their raw value
+    nb[0][:] = 0.0
+    nb[1][:] = 1.0
+    X = np.zeros((1, IN))
+    X[0, nfeat + 2] = 5.0
+    assert np.all(oracle.mlp_forward(P, X, nfeat, bf16_emulation=bf16) == 0.0)
+
+
+# ------------------------------------------------------ gate threshold pins
+def gate_setup(dT_target=0.3):
+    """A network whose output is zero (all weights and biases zero), so the
+    increments are fixed by the de-normalisation alone: mu_o = 0 for the
+    species gives dY = 0 exactly, mu_o[N] = asinh(dT / 1e-6 K) gives dT.
+    With dY = 0 the conserved state is the input state, T' = T (enthalpy
+    unchanged), so the residual |T + dT - T'| is |dT|."""
+    mech = synth.mechanism("mech53")
+    o = Oracle(mech)
+    N = mech.n_species
+    P = blank_params(N + 3)
+    _, nb = layer_views(P)
+    nb[2][N] = np.float32(np.arcsinh(dT_target / 1e-6))
+    dT = 1e-6 * np.sinh(float(nb[2][N]))
+    f = synth.field_mapped(400, seed=4)
+    i = int(np.nonzero(f.cls == 1)[0][0])
+    return o, P, nb, f.p[i], f.T[i], f.Y[:, i].copy(), dT, N
+
+
+def run_gate(o, P, p, T, Y, **kw):
+    args = dict(tau_T=1e9, y_min=-1.0, margin=0.0, max_dT=np.inf, T_max=np.inf)
+    args.update(kw)
+    return oracle.surrogate_cell(o, P, p, T, Y, 1e-6, **args)
+
+
+def assert_accept(res, T, Y):
+    ok, T1, Y1 = res
+    assert ok
+    assert abs(T1 - T) <= 1e-9 and np.array_equal(Y1, Y)
+
+
+def assert_reject(res, T, Y):
+    ok, T1, Y1 = res
+    assert not ok and T1 == T and np.array_equal(Y1, Y)
+
+
+def test_gate_residual_threshold_tau_T():
+    o, P, _, p, T, Y, dT, _ = gate_setup(0.3)
+    assert 0.29 < dT < 0.31
+    assert_accept(run_gate(o, P, p, T, Y, tau_T=dT + 1e-6), T, Y)
+    assert_reject(run_gate(o, P, p, T, Y, tau_T=dT - 1e-6), T, Y)
+
+
+def test_gate_predicted_dT_threshold():
+    o, P, _, p, T, Y, dT, _ = gate_setup(0.3)
+    assert_accept(run_gate(o, P, p, T, Y, max_dT=dT * (1 + 1e-9)), T, Y)
+    assert_reject(run_gate(o, P, p, T, Y, max_dT=dT * (1 - 1e-9)), T, Y)
+
+
+def test_gate_negative_mass_fraction_threshold_y_min():
+    """dY = 0: the conserved state equals the input, so its smallest mass
+    fraction is min Y exactly; y_min at that value passes (>=), the next
+    double above it fails."""
+    o, P, _, p, T, Y, _, _ = gate_setup(1e-3)
+    ymin = float(Y.min())
+    assert_accept(run_gate(o, P, p, T, Y, y_min=ymin), T, Y)
+    assert_reject(run_gate(o, P, p, T, Y, y_min=np.nextafter(ymin, np.inf)), T, Y)
+
+
+def test_gate_hottest_cell_threshold_T_max():
+    o, P, _, p, T, Y, _, _ = gate_setup(1e-3)
+    assert_accept(run_gate(o, P, p, T, Y, T_max=T), T, Y)
+    assert_reject(run_gate(o, P, p, T, Y, T_max=np.nextafter(T, -np.inf)), T, Y)
+
+
+def test_gate_training_box_margin():
+    """ln T lies a distance d below a box of span s: the margin reaches it
+    exactly when margin s >= d."""
+    o, P, nb, p, T, Y, _, N = gate_setup(1e-3)
+    x0 = np.log(T)
+    nb[4][:] = -1e30
+    nb[5][:] = 1e30
+    nb[4][0] = np.float32(x0 + 0.5)
+    nb[5][0] = np.float32(x0 + 1.5)
+    d = float(nb[4][0]) - x0
+    s = float(nb[5][0]) - float(nb[4][0])
+    assert d > 0.4 and s > 0.9
+    assert_accept(run_gate(o, P, p, T, Y, margin=d / s * (1 + 1e-9)), T, Y)
+    assert_reject(run_gate(o, P, p, T, Y, margin=d / s * (1 - 1e-9)), T, Y)
+    assert_reject(run_gate(o, P, p, T, Y, margin=0.0), T, Y)
+    # above the box, symmetrically
+    nb[4][0] = np.float32(x0 - 1.5)
+    nb[5][0] = np.float32(x0 - 0.5)
+    d = x0 - float(nb[5][0])
+    s = float(nb[5][0]) - float(nb[4][0])
+    assert_accept(run_gate(o, P, p, T, Y, margin=d / s * (1 + 1e-9)), T, Y)
+    assert_reject(run_gate(o, P, p, T, Y, margin=d / s * (1 - 1e-9)), T, Y)
