@@ -228,6 +228,12 @@ const char *chem_last_error(const chem_ctx *ctx);
  * [200, 10000] K, A <= 0, indices out of range, efficiencies on
  * non-third-body reactions (CHEM_E_BAD_MECHANISM).  Synchronous. */
 int chem_set_mechanism(chem_ctx *ctx, const chem_mech_desc *m);
+/* The validation of chem_set_mechanism alone, on the host: no context and
+ * no device are needed, nothing is uploaded.  Returns CHEM_OK, or
+ * CHEM_E_BAD_MECHANISM / CHEM_E_INVALID_ARG with the reason written to msg
+ * (host, nullable, msg_len bytes including the terminating zero; an empty
+ * string on success). */
+int chem_validate_mechanism(const chem_mech_desc *m, char *msg, int32_t msg_len);
 /* Largest species count the integrator handles: 137 (138 unknowns).  Up to
  * 63 species a wavefront integrates a cell with its iteration matrix in
  * registers; above that a workgroup of four wavefronts integrates a cell with

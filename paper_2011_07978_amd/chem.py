@@ -100,7 +100,7 @@ class TuneEntry(C.Structure):
 
 
 EXPORTS = ["chem_create", "chem_destroy", "chem_set_stream", "chem_last_error",
-           "chem_set_mechanism", "chem_max_species", "chem_set_options", "chem_get_options",
+           "chem_set_mechanism", "chem_validate_mechanism", "chem_max_species", "chem_set_options", "chem_get_options",
            "chem_query_slots", "chem_plan_balance",
            "chem_default_options", "chem_reserve", "chem_map_reference", "chem_integrate",
            "chem_eval_rhs_jac", "chem_rodas_step", "chem_integrate_surrogate",
@@ -131,6 +131,7 @@ def load_library(path: str = LIB_PATH):
     L.chem_last_error.argtypes = [vp]
     L.chem_last_error.restype = C.c_char_p
     L.chem_set_mechanism.argtypes = [vp, C.POINTER(MechDesc)]
+    L.chem_validate_mechanism.argtypes = [C.POINTER(MechDesc), C.c_char_p, C.c_int32]
     L.chem_max_species.argtypes = []
     L.chem_set_options.argtypes = [vp, C.POINTER(Options)]
     L.chem_get_options.argtypes = [vp, C.POINTER(Options)]
@@ -196,6 +197,45 @@ class ChemError(RuntimeError):
     pass
 
 
+def mech_desc(mech):
+    """chem_mech_desc of a mechanism object (synth.Mechanism or anything with
+    its fields), and the host arrays it points into (keep them alive)."""
+    import numpy as np
+    k = [_np(mech.elem_mass, np.float64), _np(mech.composition, np.int32), _np(mech.W, np.float64),
+         _np(mech.nasa, np.float64), _np(mech.reactants, np.int32), _np(mech.products, np.int32),
+         _np(mech.A, np.float64), _np(mech.b, np.float64), _np(mech.Ea, np.float64),
+         _np(mech.third_body, np.int32), _np(mech.eff_reaction, np.int32),
+         _np(mech.eff_species, np.int32), _np(mech.eff_value, np.float64)]
+    P = lambda a, t: a.ctypes.data_as(t)
+    fo_t = getattr(mech, "falloff", None)
+    fo_p = getattr(mech, "fo_params", None)
+    if fo_t is not None:
+        k += [_np(fo_t, np.int32), _np(fo_p, np.float64)]
+    pl_n = getattr(mech, "plog_count", None)
+    pl = []
+    if pl_n is not None:
+        pl = [_np(pl_n, np.int32), _np(mech.plog_params, np.float64)]
+        k += pl
+    d = MechDesc(int(mech.n_elements), int(mech.n_species), int(mech.n_reactions),
+                 P(k[0], _d), P(k[1], _i32), P(k[2], _d), P(k[3], _d), P(k[4], _i32),
+                 P(k[5], _i32), P(k[6], _d), P(k[7], _d), P(k[8], _d), P(k[9], _i32),
+                 int(k[12].size), P(k[10], _i32), P(k[11], _i32), P(k[12], _d),
+                 P(k[13], _i32) if fo_t is not None else None,
+                 P(k[14], _d) if fo_t is not None else None,
+                 P(pl[0], _i32) if pl else None, P(pl[1], _d) if pl else None)
+    return d, k
+
+
+def validate_mechanism(mech):
+    """chem_validate_mechanism (host only, no GPU): (return code, reason)."""
+    L = load_library()
+    d, keep = mech_desc(mech)
+    buf = C.create_string_buffer(512)
+    rc = L.chem_validate_mechanism(C.byref(d), buf, 512)
+    del keep
+    return rc, buf.value.decode()
+
+
 class Chem:
     """A libchem context on one HIP device, enqueueing on torch's current stream."""
 
@@ -231,30 +271,9 @@ class Chem:
 
     # ---------------------------------------------------------------- setup
     def set_mechanism(self, mech):
-        import numpy as np
-        k = [_np(mech.elem_mass, np.float64), _np(mech.composition, np.int32), _np(mech.W, np.float64),
-             _np(mech.nasa, np.float64), _np(mech.reactants, np.int32), _np(mech.products, np.int32),
-             _np(mech.A, np.float64), _np(mech.b, np.float64), _np(mech.Ea, np.float64),
-             _np(mech.third_body, np.int32), _np(mech.eff_reaction, np.int32),
-             _np(mech.eff_species, np.int32), _np(mech.eff_value, np.float64)]
-        P = lambda a, t: a.ctypes.data_as(t)
-        fo_t = getattr(mech, "falloff", None)
-        fo_p = getattr(mech, "fo_params", None)
-        if fo_t is not None:
-            k += [_np(fo_t, np.int32), _np(fo_p, np.float64)]
-        pl_n = getattr(mech, "plog_count", None)
-        pl = []
-        if pl_n is not None:
-            pl = [_np(pl_n, np.int32), _np(mech.plog_params, np.float64)]
-            k += pl
-        d = MechDesc(int(mech.n_elements), int(mech.n_species), int(mech.n_reactions),
-                     P(k[0], _d), P(k[1], _i32), P(k[2], _d), P(k[3], _d), P(k[4], _i32),
-                     P(k[5], _i32), P(k[6], _d), P(k[7], _d), P(k[8], _d), P(k[9], _i32),
-                     int(k[12].size), P(k[10], _i32), P(k[11], _i32), P(k[12], _d),
-                     P(k[13], _i32) if fo_t is not None else None,
-                     P(k[14], _d) if fo_t is not None else None,
-                     P(pl[0], _i32) if pl else None, P(pl[1], _d) if pl else None)
+        d, keep = mech_desc(mech)
         self._check(self.L.chem_set_mechanism(self.h, C.byref(d)), "chem_set_mechanism")
+        del keep
         self.mech = mech
         return self
 

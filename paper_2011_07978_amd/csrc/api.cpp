@@ -402,24 +402,43 @@ static std::vector<RxnSlots> order_reactions(int N, int R, const int *rea, const
     return out;
 }
 
-int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
-    if (!c || !m) return CHEM_E_INVALID_ARG;
+// Facts about a validated mechanism that the packing step reuses.
+struct MechFacts {
+    std::vector<int> is_tb;
+    std::vector<std::vector<std::pair<int, double>>> eff;   // (species, alpha - 1) per reaction
+    bool any_fo = false, any_plog = false;
+};
+
+static int bad(std::string &why, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    why = buf;
+    return code;
+}
+
+// Validation of a mechanism description, host only (no device).  Returns
+// CHEM_OK and fills *facts, or CHEM_E_INVALID_ARG / CHEM_E_BAD_MECHANISM with
+// the reason in why.
+static int check_mechanism(const chem_mech_desc *m, std::string &why, MechFacts &facts) {
     const int E = m->n_elements, N = m->n_species, R = m->n_reactions;
     if (E < 1 || E > 16 || N < 1 || N > 160 || R < 1 || R > 4096)
-        return fail(c, CHEM_E_BAD_MECHANISM, "sizes out of range (E=%d N=%d R=%d)", E, N, R);
+        return bad(why, CHEM_E_BAD_MECHANISM, "sizes out of range (E=%d N=%d R=%d)", E, N, R);
     if (!m->elem_mass || !m->composition || !m->W || !m->nasa || !m->reactants || !m->products ||
         !m->A || !m->b || !m->Ea || !m->third_body || m->n_eff < 0 ||
         (m->n_eff > 0 && (!m->eff_reaction || !m->eff_species || !m->eff_value)))
-        return fail(c, CHEM_E_INVALID_ARG, "null mechanism array");
+        return bad(why, CHEM_E_INVALID_ARG, "null mechanism array");
     // molar masses consistent with the composition
     for (int k = 0; k < N; ++k) {
         double w = 0.0;
         for (int e = 0; e < E; ++e) {
-            if (m->composition[k * E + e] < 0) return fail(c, CHEM_E_BAD_MECHANISM, "negative atom count");
+            if (m->composition[k * E + e] < 0) return bad(why, CHEM_E_BAD_MECHANISM, "negative atom count");
             w += m->composition[k * E + e] * m->elem_mass[e];
         }
         if (!(m->W[k] > 0.0) || fabs(w - m->W[k]) > 1e-9 * m->W[k])
-            return fail(c, CHEM_E_BAD_MECHANISM, "species %d: W inconsistent with composition", k);
+            return bad(why, CHEM_E_BAD_MECHANISM, "species %d: W inconsistent with composition", k);
     }
     // cp > 0 on [200, 10000] K
     for (int k = 0; k < N; ++k) {
@@ -427,10 +446,10 @@ int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
         for (int q = 0; q <= 400; ++q) {
             const double T = 200.0 + q * (9800.0 / 400.0);
             const double cp = a[0] + a[1] * T + a[2] * T * T + a[3] * T * T * T + a[4] * T * T * T * T;
-            if (!(cp > 0.0)) return fail(c, CHEM_E_BAD_MECHANISM, "species %d: cp <= 0 at %g K", k, T);
+            if (!(cp > 0.0)) return bad(why, CHEM_E_BAD_MECHANISM, "species %d: cp <= 0 at %g K", k, T);
         }
         for (int i = 0; i < 7; ++i)
-            if (!isfinite(a[i])) return fail(c, CHEM_E_BAD_MECHANISM, "species %d: non-finite thermo", k);
+            if (!isfinite(a[i])) return bad(why, CHEM_E_BAD_MECHANISM, "species %d: non-finite thermo", k);
     }
     // reactions: indices, balance, parameters
     std::vector<int> is_tb(R, 0);
@@ -439,19 +458,19 @@ int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
         std::vector<long> bal(E, 0);
         for (int s = 0; s < 2; ++s) {
             const int k = m->reactants[2 * j + s];
-            if (k < -1 || k >= N) return fail(c, CHEM_E_BAD_MECHANISM, "reaction %d: bad reactant", j);
+            if (k < -1 || k >= N) return bad(why, CHEM_E_BAD_MECHANISM, "reaction %d: bad reactant", j);
             if (k >= 0) { ++nr; for (int e = 0; e < E; ++e) bal[e] -= m->composition[k * E + e]; }
         }
         for (int s = 0; s < 3; ++s) {
             const int k = m->products[3 * j + s];
-            if (k < -1 || k >= N) return fail(c, CHEM_E_BAD_MECHANISM, "reaction %d: bad product", j);
+            if (k < -1 || k >= N) return bad(why, CHEM_E_BAD_MECHANISM, "reaction %d: bad product", j);
             if (k >= 0) { ++np; for (int e = 0; e < E; ++e) bal[e] += m->composition[k * E + e]; }
         }
-        if (nr == 0 || np == 0) return fail(c, CHEM_E_BAD_MECHANISM, "reaction %d: empty side", j);
+        if (nr == 0 || np == 0) return bad(why, CHEM_E_BAD_MECHANISM, "reaction %d: empty side", j);
         for (int e = 0; e < E; ++e)
-            if (bal[e] != 0) return fail(c, CHEM_E_BAD_MECHANISM, "reaction %d: element %d unbalanced", j, e);
+            if (bal[e] != 0) return bad(why, CHEM_E_BAD_MECHANISM, "reaction %d: element %d unbalanced", j, e);
         if (!(m->A[j] > 0.0) || !isfinite(m->A[j]) || !isfinite(m->b[j]) || !isfinite(m->Ea[j]))
-            return fail(c, CHEM_E_BAD_MECHANISM, "reaction %d: bad rate parameters", j);
+            return bad(why, CHEM_E_BAD_MECHANISM, "reaction %d: bad rate parameters", j);
         is_tb[j] = m->third_body[j] != 0;
     }
     std::vector<std::vector<std::pair<int, double>>> eff(R);
@@ -459,16 +478,16 @@ int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
         const int j = m->eff_reaction[i], k = m->eff_species[i];
         if (j < 0 || j >= R || !is_tb[j] || k < 0 || k >= N || !(m->eff_value[i] >= 0.0) ||
             !isfinite(m->eff_value[i]))
-            return fail(c, CHEM_E_BAD_MECHANISM, "bad third-body efficiency %d", i);
+            return bad(why, CHEM_E_BAD_MECHANISM, "bad third-body efficiency %d", i);
         for (auto &pr : eff[j])
-            if (pr.first == k) return fail(c, CHEM_E_BAD_MECHANISM, "duplicate efficiency %d", i);
+            if (pr.first == k) return bad(why, CHEM_E_BAD_MECHANISM, "duplicate efficiency %d", i);
         eff[j].push_back({k, m->eff_value[i] - 1.0});
     }
     // fall-off forms: third-body reactions only; finite parameters, A0 > 0,
     // Troe T3, T1 > 0
     bool any_fo = false;
     if (m->falloff) {
-        if (!m->falloff_params) return fail(c, CHEM_E_BAD_MECHANISM, "falloff without falloff_params");
+        if (!m->falloff_params) return bad(why, CHEM_E_BAD_MECHANISM, "falloff without falloff_params");
         for (int j = 0; j < R; ++j) {
             const int t = m->falloff[j];
             if (t == 0) continue;
@@ -476,7 +495,7 @@ int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
             bool ok = (t == 1 || t == 2) && is_tb[j] && f[0] > 0.0;
             for (int i = 0; i < 7; ++i) ok = ok && isfinite(f[i]);
             if (t == 2) ok = ok && f[4] > 0.0 && f[5] > 0.0;
-            if (!ok) return fail(c, CHEM_E_BAD_MECHANISM, "reaction %d: bad fall-off form", j);
+            if (!ok) return bad(why, CHEM_E_BAD_MECHANISM, "reaction %d: bad fall-off form", j);
             any_fo = true;
         }
     }
@@ -485,13 +504,13 @@ int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
         int lists = 0;
         for (int j = 0; j < R; ++j) lists += eff[j].size() > 3;
         if (TB_LIST0 + lists - 1 > TB_CODE)
-            return fail(c, CHEM_E_BAD_MECHANISM, "too many third-body efficiency lists (%d)", lists);
+            return bad(why, CHEM_E_BAD_MECHANISM, "too many third-body efficiency lists (%d)", lists);
     }
     // PLOG tables: reactions without a third body, 2..8 entries, strictly
     // increasing positive pressures, A_i > 0, finite parameters
     bool any_plog = false;
     if (m->plog_count) {
-        if (!m->plog_params) return fail(c, CHEM_E_BAD_MECHANISM, "plog_count without plog_params");
+        if (!m->plog_params) return bad(why, CHEM_E_BAD_MECHANISM, "plog_count without plog_params");
         for (int j = 0; j < R; ++j) {
             const int cnt = m->plog_count[j];
             if (cnt == 0) continue;
@@ -501,10 +520,39 @@ int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
                 for (int q = 0; q < 4; ++q) ok = ok && isfinite(t[4 * i + q]);
                 ok = ok && t[4 * i] > 0.0 && t[4 * i + 1] > 0.0 && (i == 0 || t[4 * i] > t[4 * i - 4]);
             }
-            if (!ok) return fail(c, CHEM_E_BAD_MECHANISM, "reaction %d: bad PLOG table", j);
+            if (!ok) return bad(why, CHEM_E_BAD_MECHANISM, "reaction %d: bad PLOG table", j);
             any_plog = true;
         }
     }
+
+    facts.is_tb = std::move(is_tb);
+    facts.eff = std::move(eff);
+    facts.any_fo = any_fo;
+    facts.any_plog = any_plog;
+    return CHEM_OK;
+}
+
+int chem_validate_mechanism(const chem_mech_desc *m, char *msg, int32_t msg_len) {
+    if (!m) return CHEM_E_INVALID_ARG;
+    std::string why;
+    MechFacts facts;
+    const int rc = check_mechanism(m, why, facts);
+    if (msg && msg_len > 0) snprintf(msg, (size_t)msg_len, "%s", rc ? why.c_str() : "");
+    return rc;
+}
+
+int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
+    if (!c || !m) return CHEM_E_INVALID_ARG;
+    MechFacts facts;
+    {
+        std::string why;
+        const int rc = check_mechanism(m, why, facts);
+        if (rc) return fail(c, rc, "%s", why.c_str());
+    }
+    const int E = m->n_elements, N = m->n_species, R = m->n_reactions;
+    const std::vector<int> &is_tb = facts.is_tb;
+    const auto &eff = facts.eff;
+    const bool any_fo = facts.any_fo, any_plog = facts.any_plog;
 
     HIPCHK(c, hipSetDevice(c->device));
     free_mech(c);
