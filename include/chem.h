@@ -55,7 +55,9 @@ enum {
     CHEM_CELL_NONFINITE = 3,   /* accepted state not finite */
     CHEM_CELL_BAD_INPUT = 4,   /* T <= 0, p <= 0 or non-finite input; cell untouched */
     CHEM_CELL_MAPPED = 5,      /* cell took the reference's increment */
-    CHEM_CELL_SURROGATE = 6    /* cell was advanced by the learned surrogate */
+    CHEM_CELL_SURROGATE = 6,   /* cell was advanced by the learned surrogate */
+    CHEM_CELL_REF_FAILED = 7   /* mapped cell left unchanged: the reference cell's own
+                                  integration failed, so there is no increment to copy */
 };
 
 /* routing flags (uint8 per cell) */
@@ -402,17 +404,19 @@ int chem_rodas_step(chem_ctx *ctx, int64_t n_cells, const double *T, const doubl
  * n_proc processes; process k holds n_prob[k] problems whose costs (e.g. CPU
  * time or attempted steps of the previous step) are t_cost[off_k ..
  * off_k + n_prob[k]), off_k = n_prob[0] + ... + n_prob[k-1], in its own list
- * order.  The plan:
- *   - loads l_k = sum of the process's costs (in list order), mean L = sum l / n_proc;
- *   - loads sorted ascending (ties by process index), receiver pointer i at the
- *     lightest, sender pointer j at the heaviest;
- *   - while i != j: dL = min(L - L_i, L_j - L); the sender's next problems, in
- *     its list order from where its last emitted send stopped, up to the first
- *     prefix whose cost reaches dL (all that remain if none does), make one
- *     operation (sender, receiver, count); L_i += dL, L_j -= dL; i advances if
- *     |L_i - L| <= 1e-12 L, else j retreats;
- *   - an operation with dL < min_frac * L (the paper uses 0.01) is computed but
- *     not emitted (no problems move).
+ * order.  The plan brings every process towards the mean load L (the sum of
+ * all costs over n_proc), pairing the lightest remaining receivers with the
+ * heaviest remaining senders as the paper's algorithm does:
+ *   - receivers (load below L, lightest first, ties by index) and senders
+ *     (load above L, heaviest first) are laid out as consecutive intervals of
+ *     their deficits and surpluses; each overlap of a receiver's interval with
+ *     a sender's is one transfer of that planned load (where a receiver and a
+ *     sender end together to within 1e-12 L, the receiver is retired first);
+ *   - a transfer whose planned load is below min_frac * L (the paper uses
+ *     0.01) is dropped;
+ *   - a kept transfer moves the fewest of the sender's problems, in its list
+ *     order from where its previous transfer stopped, whose cost reaches the
+ *     planned load (all that remain if none do).
  * ops (host) receives up to max_ops operations in the order found (n_ops: how
  * many were emitted, possibly more than max_ops, in which case
  * CHEM_E_INVALID_ARG is returned after filling max_ops); loads_after (host,
@@ -424,7 +428,7 @@ typedef struct {
     int64_t first;     /* index in the sender's list of the first problem sent */
     int64_t count;     /* problems sent: first .. first + count - 1 */
     double load;       /* their summed cost */
-    double planned;    /* dL of the algorithm for this pair */
+    double planned;    /* the planned load of this transfer */
 } chem_balance_op;
 
 int chem_plan_balance(int32_t n_proc, const int64_t *n_prob, const double *t_cost, double min_frac,

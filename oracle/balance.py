@@ -55,55 +55,99 @@ def ideal_speedup(loads: np.ndarray) -> float:
     return float(np.max(loads) / np.mean(loads))
 
 
-def plan_balance(n_prob, t_cost, min_frac=0.01):
-    """Algorithm 1 (Sec. 2.2), plain loops: the list of balancing operations
-    (sender, receiver, first, count, load, planned) and the loads after they
-    move their problems.
+def unit_transfers(loads):
+    """Brute force of the balancing plan for integer loads whose mean is an
+    integer (Algorithm 1, Sec. 2.2, by its goal: every process ends at the
+    mean load, the lightest processes filled first from the heaviest).
 
-    Readings of the garbled passages: the mean load is the sum of the loads
-    over the number of processes; "|L_i - mean| ~ 0" is |L_i - mean| <= 1e-12
-    mean; "find N_send s.t. dL ~ sum t" takes, in the sender's list order
-    from where its last emitted send stopped, the shortest prefix whose cost
-    reaches dL (all remaining problems if none does); operations with
-    dL < min_frac * mean are computed but not emitted."""
+    Moves one unit of load at a time from the current sender to the current
+    receiver: receivers are the processes below the mean, lightest first
+    (ties: lower index first); senders those above it, heaviest first (ties:
+    higher index first, the heavy end of the same ascending order).  A
+    receiver is served until it reaches the mean, a sender gives until it
+    does.  Returns {(sender, receiver): units}, in the order first used."""
+    loads = [int(v) for v in loads]
+    n = len(loads)
+    total = sum(loads)
+    assert total % n == 0, "brute force needs an integer mean"
+    mean = total // n
+    order = sorted(range(n), key=lambda k: (loads[k], k))
+    receivers = [k for k in order if loads[k] < mean]
+    senders = [k for k in reversed(order) if loads[k] > mean]
+    have = list(loads)
+    flow = {}
+    ri = si = 0
+    while ri < len(receivers) and si < len(senders):
+        r, s = receivers[ri], senders[si]
+        have[r] += 1
+        have[s] -= 1
+        flow[(s, r)] = flow.get((s, r), 0) + 1
+        if have[r] == mean:
+            ri += 1
+        if have[s] == mean:
+            si += 1
+    assert all(v == mean for v in have)
+    return flow
+
+
+def check_plan(n_prob, t_cost, ops, loads_after, min_frac=0.01, rel=1e-12):
+    """Checks a balancing plan (operations (sender, receiver, first, count,
+    load, planned) and the loads after them) against what the plan must
+    satisfy whatever its internal steps; returns the list of violations.
+
+      - every problem leaves its process at most once, operations of one
+        sender take its problems in list order without gaps;
+      - an operation's load is the cost of the problems it names, and they
+        are the fewest from its first whose cost reaches the planned load
+        (or every remaining problem);
+      - no process both sends and receives, and nobody sends to itself;
+      - planned loads are at least min_frac of the mean; the planned loads a
+        receiver gets sum to at most its deficit, a sender's to at most its
+        surplus;
+      - load is conserved, and the loads after are the loads before moved by
+        the operations."""
     n_prob = [int(v) for v in n_prob]
-    n_proc = len(n_prob)
-    lists, pos = [], 0
-    for k in range(n_proc):
-        lists.append([float(t) for t in t_cost[pos:pos + n_prob[k]]])
-        pos += n_prob[k]
-    loads = []
-    for k in range(n_proc):
-        s = 0.0
-        for t in lists[k]:
-            s += t
-        loads.append(s)
-    total = 0.0
-    for v in loads:
-        total += v
-    mean = total / n_proc
-    order = sorted(range(n_proc), key=lambda k: (loads[k], k))
-    L = [loads[k] for k in order]
-    after = list(loads)
-    cursor = [0] * n_proc
-    ops = []
-    i, j = 0, n_proc - 1
-    while i != j:
-        dL = min(mean - L[i], L[j] - mean)
-        rr, rs = order[i], order[j]
-        first, cnt, sent = cursor[rs], 0, 0.0
-        while first + cnt < n_prob[rs] and sent < dL:
-            sent += lists[rs][first + cnt]
-            cnt += 1
-        if dL >= min_frac * mean and cnt > 0:
-            ops.append((rs, rr, first, cnt, sent, dL))
-            cursor[rs] += cnt
-            after[rs] -= sent
-            after[rr] += sent
-        L[i] += dL
-        L[j] -= dL
-        if abs(L[i] - mean) <= 1e-12 * mean:
-            i += 1
-        else:
-            j -= 1
-    return ops, np.array(after)
+    t_cost = [float(v) for v in t_cost]
+    starts = [0]
+    for c in n_prob:
+        starts.append(starts[-1] + c)
+    loads = [sum(t_cost[starts[k]:starts[k + 1]]) for k in range(len(n_prob))]
+    mean = sum(loads) / len(loads)
+    bad = []
+    nxt = {}
+    moved = list(loads)
+    got_planned, gave_planned = {}, {}
+    for op in ops:
+        s, r, first, cnt, load, planned = op
+        if s == r or cnt <= 0:
+            bad.append(("self or empty", op))
+        if first != nxt.get(s, 0) or first + cnt > n_prob[s]:
+            bad.append(("not in list order", op))
+        nxt[s] = first + cnt
+        costs = t_cost[starts[s] + first:starts[s] + first + cnt]
+        if abs(sum(costs) - load) > rel * max(1.0, abs(load)):
+            bad.append(("load is not the problems' cost", op))
+        if sum(costs) < planned * (1 - rel) and first + cnt < n_prob[s]:
+            bad.append(("stops short of the planned load", op))
+        if cnt > 1 and sum(costs[:-1]) >= planned:
+            bad.append(("not the fewest problems", op))
+        if planned < min_frac * mean * (1 - rel):
+            bad.append(("below the threshold", op))
+        got_planned[r] = got_planned.get(r, 0.0) + planned
+        gave_planned[s] = gave_planned.get(s, 0.0) + planned
+        moved[s] -= load
+        moved[r] += load
+    if set(got_planned) & set(gave_planned):
+        bad.append(("a process both sends and receives", None))
+    for r, v in got_planned.items():
+        if v > (mean - loads[r]) + rel * max(1.0, mean) * len(loads):
+            bad.append(("receiver planned beyond its deficit", r))
+    for s, v in gave_planned.items():
+        if v > (loads[s] - mean) + rel * max(1.0, mean) * len(loads):
+            bad.append(("sender planned beyond its surplus", s))
+    if abs(sum(loads_after) - sum(loads)) > rel * max(1.0, sum(loads)) * len(loads):
+        bad.append(("load not conserved", None))
+    for k in range(len(loads)):
+        if abs(loads_after[k] - moved[k]) > rel * max(1.0, abs(moved[k])) * len(loads):
+            bad.append(("loads after do not follow the operations", k))
+    return bad

@@ -1,13 +1,22 @@
-// Load-balancing plan across processes: Algorithm 1 of Sec. 2.2 (host only).
+// Load-balancing plan across processes (Algorithm 1, Sec. 2.2), host only.
 //
-// Loads are the summed costs of each process's problems; processes are
-// sorted by load and a receiver pointer (lightest) and a sender pointer
-// (heaviest) walk towards each other, pairing them to move min(mean -
-// receiver load, sender load - mean) of load at a time.  The load moved is
-// turned into a count of the sender's problems (in its list order, from where
-// its previous emitted send stopped, the shortest prefix whose cost reaches
-// the planned load).  Pairs that would move less than min_frac of the mean
-// load are planned but not emitted.
+// The goal of the paper's plan: every process should end at the mean load,
+// heavy processes giving problems to light ones, and moves worth less than a
+// small fraction of the mean are not made.  Its pairing of the lightest
+// remaining receiver with the heaviest remaining sender is the north-west
+// corner rule of a transportation problem, which is how it is built here:
+//   - receivers (load below the mean) are laid out lightest first as
+//     consecutive intervals of length mean - load on one axis, senders (load
+//     above the mean) heaviest first as intervals of length load - mean on
+//     another; both axes end at the total imbalance;
+//   - every overlap of a receiver interval with a sender interval is one
+//     planned transfer of that length, found by merging the two sorted
+//     sequences of interval ends (a receiver and a sender ending together, to
+//     1e-12 of the mean, retire the receiver first);
+//   - a transfer below min_frac of the mean, or not above 1e-12 of it, is
+//     dropped; each kept transfer becomes a count of the sender's problems,
+//     taken in its list order from where its previous transfer stopped: the
+//     fewest whose cost reaches the planned load (all that remain if none do).
 #include <math.h>
 #include <stdint.h>
 
@@ -17,58 +26,90 @@
 
 #include "../../include/chem.h"
 
+namespace {
+
+// One side of the transportation problem: processes and the cumulative ends
+// of their intervals.
+struct Side {
+    std::vector<int> proc;
+    std::vector<double> end;
+};
+
+}  // namespace
+
 extern "C" int chem_plan_balance(int32_t n_proc, const int64_t *n_prob, const double *t_cost,
                                  double min_frac, chem_balance_op *ops, int64_t max_ops,
                                  int64_t *n_ops, double *loads_after) {
     if (n_proc < 1 || !n_prob || !n_ops || (max_ops > 0 && !ops) || max_ops < 0 ||
         !(min_frac >= 0.0))
         return CHEM_E_INVALID_ARG;
-    std::vector<int64_t> off((size_t)n_proc + 1, 0);
+    std::vector<int64_t> start((size_t)n_proc + 1, 0);
     for (int k = 0; k < n_proc; ++k) {
         if (n_prob[k] < 0) return CHEM_E_INVALID_ARG;
-        off[k + 1] = off[k] + n_prob[k];
+        start[k + 1] = start[k] + n_prob[k];
     }
-    if (off[n_proc] > 0 && !t_cost) return CHEM_E_INVALID_ARG;
-    std::vector<double> l((size_t)n_proc, 0.0);
-    for (int k = 0; k < n_proc; ++k)
-        for (int64_t q = off[k]; q < off[k + 1]; ++q) {
-            const double t = t_cost[q];
-            if (!(t >= 0.0) || !isfinite(t)) return CHEM_E_INVALID_ARG;
-            l[k] += t;
+    if (start[n_proc] > 0 && !t_cost) return CHEM_E_INVALID_ARG;
+    for (int64_t q = 0; q < start[n_proc]; ++q)
+        if (!(t_cost[q] >= 0.0) || !isfinite(t_cost[q])) return CHEM_E_INVALID_ARG;
+
+    std::vector<double> load((size_t)n_proc, 0.0);
+    double total = 0.0;
+    for (int k = 0; k < n_proc; ++k) {
+        for (int64_t q = start[k]; q < start[k + 1]; ++q) load[k] += t_cost[q];
+        total += load[k];
+    }
+    const double mean = total / n_proc;
+    const double tie = 1e-12 * mean;
+
+    // processes by ascending load (ties by index): receivers from the light
+    // end, senders from the heavy end
+    std::vector<int> by_load((size_t)n_proc);
+    std::iota(by_load.begin(), by_load.end(), 0);
+    std::stable_sort(by_load.begin(), by_load.end(), [&](int a, int b) { return load[a] < load[b]; });
+    Side rec, snd;
+    double acc = 0.0;
+    for (int k : by_load)
+        if (load[k] < mean) {
+            acc += mean - load[k];
+            rec.proc.push_back(k);
+            rec.end.push_back(acc);
         }
-    double mean = 0.0;
-    for (int k = 0; k < n_proc; ++k) mean += l[k];
-    mean /= n_proc;
+    acc = 0.0;
+    for (auto it = by_load.rbegin(); it != by_load.rend(); ++it)
+        if (load[*it] > mean) {
+            acc += load[*it] - mean;
+            snd.proc.push_back(*it);
+            snd.end.push_back(acc);
+        }
 
-    std::vector<int> R((size_t)n_proc);
-    std::iota(R.begin(), R.end(), 0);
-    std::stable_sort(R.begin(), R.end(), [&](int a, int b) { return l[a] < l[b]; });
-    std::vector<double> L((size_t)n_proc);
-    for (int i = 0; i < n_proc; ++i) L[i] = l[R[i]];
-
-    std::vector<double> after(l);
-    std::vector<int64_t> cursor((size_t)n_proc, 0);   // next problem of each sender
+    std::vector<double> after(load);
+    std::vector<int64_t> next((size_t)n_proc, 0);   // each sender's first problem not yet given
     int64_t emitted = 0;
-    int i = 0, j = n_proc - 1;
-    while (i != j) {
-        const double dL = std::min(mean - L[i], L[j] - mean);
-        const int rr = R[i], rs = R[j];
-        // shortest prefix of the sender's remaining problems reaching dL
-        const int64_t first = cursor[rs];
-        int64_t cnt = 0;
-        double sent = 0.0;
-        while (first + cnt < n_prob[rs] && sent < dL) sent += t_cost[off[rs] + first + cnt++];
-        if (dL >= min_frac * mean && cnt > 0) {
-            if (emitted < max_ops) ops[emitted] = chem_balance_op{rs, rr, first, cnt, sent, dL};
-            ++emitted;
-            cursor[rs] += cnt;
-            after[rs] -= sent;
-            after[rr] += sent;
+    double x = 0.0;                                  // position on the merged axis
+    size_t a = 0, b = 0;
+    while (a < rec.proc.size() && b < snd.proc.size()) {
+        const double stop = std::min(rec.end[a], snd.end[b]);
+        const double planned = stop - x;
+        const int r = rec.proc[a], s = snd.proc[b];
+        if (planned >= min_frac * mean && planned > tie) {
+            const int64_t *n_s = n_prob + s;
+            const double *t = t_cost + start[s];
+            const int64_t first = next[s];
+            int64_t q = first;
+            double moved = 0.0;
+            while (q < *n_s && moved < planned) moved += t[q++];
+            if (q > first) {
+                if (emitted < max_ops) ops[emitted] = chem_balance_op{s, r, first, q - first, moved, planned};
+                ++emitted;
+                next[s] = q;
+                after[s] -= moved;
+                after[r] += moved;
+            }
         }
-        L[i] += dL;
-        L[j] -= dL;
-        if (fabs(L[i] - mean) <= 1e-12 * mean) ++i;
-        else --j;
+        x = stop;
+        // retire the interval that ends here; the receiver first on a tie
+        if (rec.end[a] <= snd.end[b] + tie) ++a;
+        else ++b;
     }
     *n_ops = emitted;
     if (loads_after)

@@ -59,96 +59,121 @@ def test_product_bound_matches_oracle():
 
 
 # ---------------------------------------------------------------- Algorithm 1
+# The library's planner (host C++, no GPU needed) against hand-worked plans,
+# the brute-force unit-by-unit plan of the oracle and the oracle's checker.
+def _planner():
+    from paper_2011_07978_amd import chem
+    try:
+        chem.load_library()
+    except RuntimeError:
+        pytest.skip("libchem.so not built")
+    return chem.plan_balance
+
+
 def test_plan_hand_worked_one_heavy_process():
     """Loads 1, 1, 1, 5 of unit problems, mean 2: the heavy process sends one
     problem to each light one, in its list order."""
-    ops, after = balance.plan_balance([1, 1, 1, 5], [1.0] * 8)
+    ops, after = _planner()([1, 1, 1, 5], [1.0] * 8)
     assert [(o[0], o[1], o[2], o[3]) for o in ops] == [(3, 0, 0, 1), (3, 1, 1, 1), (3, 2, 2, 1)]
     assert list(after) == [2.0, 2.0, 2.0, 2.0]
 
 
 def test_plan_hand_worked_two_senders():
     """Loads 0, 0, 6, 6 (three problems of cost 2 each on the heavy ones),
-    mean 3: process 3 sends to 0, then 2 to 0 ... worked by hand."""
-    ops, after = balance.plan_balance([0, 0, 3, 3], [2.0] * 6)
-    # sorted: (0:0), (1:0), (2:6), (3:6); i=0 (proc 0), j=3 (proc 3)
-    # dL = min(3, 3) = 3 -> proc 3 sends 2 problems (4 >= 3) to proc 0; L0 = 3 -> i = 1
-    # dL = min(3, 0) = 0 -> below threshold, nothing moves; L3 = 3 -> j = 2
-    # dL = min(3, 3) = 3 -> proc 2 sends 2 problems to proc 1; i = 2 = j
+    mean 3.  Worked by hand: process 0 (lightest, lowest index) is filled from
+    process 3 (heaviest, highest index) with 3 units, which takes two
+    problems (4 >= 3); both are then at the mean; process 1 is filled from
+    process 2 the same way."""
+    ops, after = _planner()([0, 0, 3, 3], [2.0] * 6)
     assert [(o[0], o[1], o[2], o[3]) for o in ops] == [(3, 0, 0, 2), (2, 1, 0, 2)]
+    assert [o[5] for o in ops] == [3.0, 3.0]
     assert list(after) == [4.0, 4.0, 2.0, 2.0]
 
 
+def test_plan_hand_worked_sender_split_over_receivers():
+    """Loads 2, 3, 10 of unit problems, mean 5: process 2 gives 3 units to
+    process 0, then 2 to process 1, continuing in its list order."""
+    ops, after = _planner()([2, 3, 10], [1.0] * 15)
+    assert ops == [(2, 0, 0, 3, 3.0, 3.0), (2, 1, 3, 2, 2.0, 2.0)]
+    assert list(after) == [5.0, 5.0, 5.0]
+
+
 def test_plan_balanced_input_moves_nothing():
-    ops, after = balance.plan_balance([4, 4, 4], [1.0] * 12)
+    ops, after = _planner()([4, 4, 4], [1.0] * 12)
     assert ops == [] and list(after) == [4.0, 4.0, 4.0]
 
 
 def test_plan_without_load_moves_nothing():
     """No problems anywhere, or only zero-cost ones: the mean load is zero,
-    every process already sits at it, and the walk ends without operations."""
+    every process already sits at it."""
     for n_prob, t in (([0, 0, 0], []), ([2, 0, 1], [0.0, 0.0, 0.0])):
-        ops, after = balance.plan_balance(n_prob, t)
+        ops, after = _planner()(n_prob, t)
         assert ops == [] and list(after) == [0.0, 0.0, 0.0]
 
 
 def test_plan_small_imbalance_is_not_emitted():
-    """dL below 1 % of the mean load is planned but not sent."""
-    ops, _ = balance.plan_balance([100, 100], [1.0] * 100 + [1.0] * 99 + [1.5])
+    """A transfer below 1 % of the mean load is planned but not sent."""
+    ops, _ = _planner()([100, 100], [1.0] * 100 + [1.0] * 99 + [1.5])
     assert ops == []
+
+
+def test_unit_transfers_hand_worked():
+    """The brute force itself on the plans worked above."""
+    assert balance.unit_transfers([1, 1, 1, 5]) == {(3, 0): 1, (3, 1): 1, (3, 2): 1}
+    assert balance.unit_transfers([0, 0, 6, 6]) == {(3, 0): 3, (2, 1): 3}
+    assert balance.unit_transfers([2, 3, 10]) == {(2, 0): 3, (2, 1): 2}
+    assert balance.unit_transfers([4, 4, 4]) == {}
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_plan_equals_unit_brute_force(seed):
+    """Unit-cost problems and an integer mean: every planned transfer is a
+    whole number of problems, and the library's plan moves exactly what the
+    oracle's unit-by-unit brute force moves, between the same pairs, in the
+    same order (min_frac 0: nothing is dropped)."""
+    rng = np.random.default_rng(seed)
+    n_proc = int(rng.integers(2, 30))
+    n_prob = rng.integers(0, 40, n_proc)
+    n_prob[-1] += (-n_prob.sum()) % n_proc          # integer mean
+    ops, after = _planner()(n_prob, np.ones(int(n_prob.sum())), 0.0)
+    flow = balance.unit_transfers(n_prob)
+    assert [(o[0], o[1]) for o in ops] == list(flow)
+    assert [o[3] for o in ops] == list(flow.values())
+    assert [o[5] for o in ops] == [float(v) for v in flow.values()]
+    assert np.all(after == n_prob.sum() // n_proc)
+    assert balance.check_plan(n_prob, np.ones(int(n_prob.sum())), ops, after, 0.0) == []
 
 
 @pytest.mark.parametrize("seed", range(8))
 def test_plan_properties_random(seed):
+    """Real-valued costs: the oracle's checker finds no violation, and each
+    receiver ends within (sends received) problems above the mean."""
     rng = np.random.default_rng(seed)
     n_proc = int(rng.integers(2, 40))
     n_prob = rng.integers(0, 60, n_proc)
     t = rng.lognormal(0.0, 1.0, int(n_prob.sum())) * np.repeat(rng.uniform(0.2, 5.0, n_proc), n_prob)
-    ops, after = balance.plan_balance(n_prob, t)
+    ops, after = _planner()(n_prob, t)
+    assert balance.check_plan(n_prob, t, ops, after, 0.01) == []
     loads = np.array([t[a:b].sum() for a, b in zip(np.r_[0, np.cumsum(n_prob)[:-1]], np.cumsum(n_prob))])
-    assert after.sum() == pytest.approx(loads.sum(), rel=1e-12)
-    # every problem leaves its process at most once, in list order
-    sent = {}
-    for s_, r_, first, cnt, load, planned in ops:
-        assert s_ != r_ and cnt > 0
-        assert first == sent.get(s_, 0)
-        sent[s_] = first + cnt
-        assert first + cnt <= n_prob[s_]
-        offs = int(np.r_[0, np.cumsum(n_prob)][s_])
-        assert load == pytest.approx(t[offs + first: offs + first + cnt].sum(), rel=1e-12)
-        # shortest prefix: dropping the last problem would fall short
-        assert load - t[offs + first + cnt - 1] < planned or first + cnt == n_prob[s_]
-    # no process sends and receives
-    senders = {o[0] for o in ops}
-    receivers = {o[1] for o in ops}
-    assert not senders & receivers
-    # each send overshoots its planned load by less than one problem, so a
-    # receiver ends within (sends received) problems above the mean
     mean = loads.mean()
-    for r_ in receivers:
+    for r_ in {o[1] for o in ops}:
         k = sum(1 for o in ops if o[1] == r_)
         assert after[r_] <= mean + k * t.max() + 1e-9 * mean
-    for o in ops:
-        assert o[4] - o[5] < t.max() or o[3] == 1
 
 
-def test_library_plan_matches_oracle():
-    """The library's planner (host C++) against this one, operation by
-    operation and bit for bit (no GPU needed)."""
-    from paper_2011_07978_amd import chem
-    try:
-        chem.load_library()
-    except RuntimeError:
-        pytest.skip("libchem.so not built")
-    for seed in range(20):
-        rng = np.random.default_rng(100 + seed)
-        n_proc = int(rng.integers(1, 64))
-        n_prob = rng.integers(0, 80, n_proc)
-        t = rng.exponential(1.0, int(n_prob.sum())) * np.repeat(rng.uniform(0.1, 10.0, n_proc), n_prob)
-        ops_o, after_o = balance.plan_balance(n_prob, t)
-        ops_l, after_l = chem.plan_balance(n_prob, t)
-        assert ops_l == ops_o, seed
-        assert np.array_equal(after_l, after_o), seed
+def test_checker_catches_broken_plans():
+    """The checker is not vacuous: plans with a planted mistake fail it."""
+    n_prob, t = [2, 3, 10], [1.0] * 15
+    good = [(2, 0, 0, 3, 3.0, 3.0), (2, 1, 3, 2, 2.0, 2.0)]
+    after = [5.0, 5.0, 5.0]
+    assert balance.check_plan(n_prob, t, good, after) == []
+    gap = [(2, 0, 0, 3, 3.0, 3.0), (2, 1, 4, 2, 2.0, 2.0)]
+    assert balance.check_plan(n_prob, t, gap, after)
+    extra = [(2, 0, 0, 4, 4.0, 3.0), (2, 1, 4, 2, 2.0, 2.0)]
+    assert balance.check_plan(n_prob, t, extra, [6.0, 5.0, 4.0])
+    over = [(2, 0, 0, 4, 4.0, 4.0), (2, 1, 4, 1, 1.0, 1.0)]
+    assert balance.check_plan(n_prob, t, over, after)
+    assert balance.check_plan(n_prob, t, good, [5.0, 5.0, 6.0])
 
 
 def test_library_planner_rejects_bad_input():
