@@ -253,15 +253,24 @@ class Oracle:
         return T, Y
 
     def step_mapped(self, T, p, Y, dt, flags, ref, h=None, threads=0, **kw):
-        """Full oracle step with reference mapping: integrate flags 0/1, map flags 2."""
+        """Full oracle step with reference mapping (Sec. 2.3): integrate flags
+        0/1, then give flag-2 cells the reference's increment (status 5).  If
+        the reference's own integration failed (status != 0) there is no
+        solution to copy: flag-2 cells keep their state and take status 7.
+        Returns (T, Y, h, status, n_acc, n_rej)."""
         if ref < 0:
             return self.integrate_batch(T, p, Y, dt, h=h, threads=threads, **kw)
         Yref_old = _f64(Y)[:, ref].copy()
         out = self.integrate_batch(T, p, Y, dt, h=h, flags=flags, threads=threads, **kw)
-        T2, Y2 = out[0], out[1]
+        T2, Y2, h2, st = out[0], out[1], out[2], out[3].copy()
+        mapped = np.asarray(flags) == 2
+        if st[ref] != 0:
+            st[mapped] = 7
+            return (T2, Y2, h2, st) + tuple(out[4:])
         Yref_new = Y2[:, ref].copy()
         T3, Y3 = self.map_scatter(T2, Y2, flags, Yref_old, Yref_new)
-        return (T3, Y3) + tuple(out[2:])
+        st[mapped] = 5
+        return (T3, Y3, h2, st) + tuple(out[4:])
 
 
 # ----------------------------------------------------------------- surrogate

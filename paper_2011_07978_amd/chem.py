@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libchem.so")
 
 CHEM_SCHED_PLAIN, CHEM_SCHED_QUEUE, CHEM_SCHED_BLOCKS = 0, 1, 2
 (CELL_OK, CELL_MAX_STEPS, CELL_H_UNDERFLOW, CELL_NONFINITE, CELL_BAD_INPUT, CELL_MAPPED,
- CELL_SURROGATE) = range(7)
+ CELL_SURROGATE, CELL_REF_FAILED) = range(8)
 FLAG_SOLVE, FLAG_REFERENCE, FLAG_MAPPED, FLAG_SURROGATE = range(4)
 
 _d = C.POINTER(C.c_double)

@@ -28,7 +28,7 @@ hipError_t launch_map(int64_t ncells, int N, const double *T, const double *Y, c
                       double beta_f, double beta_ox, double Z_tol, double T_tol, int use_T,
                       uint8_t *flags, unsigned long long *ref_tmp, int64_t *ref_out, hipStream_t s);
 hipError_t launch_queue_reset(int *hist, int *cursor, int *seg_ctr, int *n_active,
-                              unsigned long long *stats, hipStream_t s);
+                              unsigned long long *stats, int *ref_status, hipStream_t s);
 hipError_t launch_queue_build(int64_t ncells, const uint8_t *flags, const uint32_t *cost, int *hist,
                               int *cursor, int *n_active, int *queue, hipStream_t s);
 hipError_t launch_ref_snapshot(int64_t ncells, int N, const double *T, const double *Y,
@@ -45,7 +45,8 @@ hipError_t launch_big_rodas_step(const MechDev &M, const MechDev *Md, const IntP
 hipError_t launch_map_scatter(int64_t ncells, int N, double *T, double *Y, const uint8_t *flags,
                               const int64_t *ref, const double *snap, double *delta,
                               const double *nasa_t, const double *invW, uint8_t *status,
-                              uint32_t *cost, unsigned long long *stats, hipStream_t s);
+                              uint32_t *cost, unsigned long long *stats, const int *ref_status,
+                              hipStream_t s);
 }  // namespace chem
 
 using namespace chem;
@@ -71,7 +72,7 @@ struct chem_ctx {
     // workspace
     int64_t cap = 0;
     int *d_queue = nullptr;
-    int *d_small = nullptr;        // hist[32] cursor[32] seg[8] n_active[1]
+    int *d_small = nullptr;        // hist[32] cursor[32] seg[8] n_active[1] . ref_status[76]
     unsigned long long *d_stats = nullptr;   // [8]
     unsigned long long *d_reftmp = nullptr;
     double *d_snap = nullptr, *d_delta = nullptr;
@@ -842,7 +843,8 @@ static int integrate_core(chem_ctx *c, int64_t n, double *T, const double *p, do
     hipStream_t s = c->stream;
     if (stats) HIPCHK(c, hipEventRecord(c->ev0, s));
     int *hist = c->d_small, *cursor = c->d_small + 32, *seg = c->d_small + 64, *nact = c->d_small + 72;
-    HIPCHK(c, launch_queue_reset(hist, cursor, seg, nact, c->d_stats, s));
+    int *ref_status = c->d_small + 76;
+    HIPCHK(c, launch_queue_reset(hist, cursor, seg, nact, c->d_stats, ref_status, s));
     if (n > 0) {
         if (gate) {
             if (stats) HIPCHK(c, hipEventRecord(c->ev4, s));
@@ -865,6 +867,7 @@ static int integrate_core(chem_ctx *c, int64_t n, double *T, const double *p, do
         P.T = T; P.p = p; P.Y = Y; P.h = h; P.cost = cost; P.status = status; P.steps = steps;
         P.flags = flags;
         P.stats = c->d_stats;
+        P.ref_status = ref_status;
         int grid = 0;
         if (c->big) {
             const int per_cu = c->opt.slots_per_cu > 0 ? std::min(c->opt.slots_per_cu, c->occ) : c->occ;
@@ -898,7 +901,8 @@ static int integrate_core(chem_ctx *c, int64_t n, double *T, const double *p, do
         if (stats) HIPCHK(c, hipEventRecord(c->ev3, s));
         if (flags)
             HIPCHK(c, launch_map_scatter(n, c->N, T, Y, flags, ref_index, c->d_snap, c->d_delta,
-                                         c->M.nasa_t, c->M.invW, status, cost, c->d_stats, s));
+                                         c->M.nasa_t, c->M.invW, status, cost, c->d_stats,
+                                         ref_status, s));
     }
     if (!stats) return CHEM_OK;
     HIPCHK(c, hipEventRecord(c->ev1, s));

@@ -554,6 +554,7 @@ __device__ __forceinline__ void integrate_cell(const MechDev *__restrict__ M, co
     if (bad_in) {
         if (lane == 0) {
             if (P.status) P.status[cell] = 4;
+            if (P.ref_status && P.flags && P.flags[cell] == 1) *P.ref_status = 4;
             if (P.steps) { P.steps[2 * cell] = 0; P.steps[2 * cell + 1] = 0; }
             if (P.cost) P.cost[cell] = 0;
             atomicAdd(&P.stats[0], 1ull);
@@ -607,6 +608,7 @@ __device__ __forceinline__ void integrate_cell(const MechDev *__restrict__ M, co
         if (P.h) P.h[cell] = hnext;
         if (P.cost) P.cost[cell] = (uint32_t)(nacc + nrej);
         if (P.status) P.status[cell] = (uint8_t)status;
+        if (P.ref_status && P.flags && P.flags[cell] == 1) *P.ref_status = status;
         if (P.steps) { P.steps[2 * cell] = nacc; P.steps[2 * cell + 1] = nrej; }
         atomicAdd(&P.stats[0], 1ull);
         atomicAdd(&P.stats[1], (unsigned long long)nacc);

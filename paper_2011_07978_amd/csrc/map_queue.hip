@@ -88,14 +88,22 @@ __global__ void k_ref_delta(int64_t ncells, int N, const double *__restrict__ Y,
 // Mapped cells: Y' = Y + dY_ref and T' from h(T', Y') = h(T, Y).  The mixture
 // enthalpy is a polynomial in T whose coefficients sum_k Y_k c_km / W_k are
 // gathered in one pass over the species; Newton on it to |dT| < 1e-10 K.
+// If the reference cell's own integration failed (ref_status != 0: step
+// limit, step underflow, non-finite or bad input) its increment is not a
+// solution, so mapped cells keep their state and take status 7 (counted as
+// failed) instead of inheriting it.
 __global__ __launch_bounds__(MAP_BLOCK) void k_map_scatter(
     int64_t ncells, int N, double *__restrict__ T, double *__restrict__ Y,
     const uint8_t *__restrict__ flags, const int64_t *ref, const double *__restrict__ delta,
     const double *__restrict__ nasa_t, const double *__restrict__ invW, uint8_t *status,
-    uint32_t *cost, unsigned long long *stats) {
+    uint32_t *cost, unsigned long long *stats, const int *ref_status) {
     const int64_t i = (int64_t)blockIdx.x * MAP_BLOCK + threadIdx.x;
-    bool mapped = false;
-    if (i < ncells && *ref >= 0 && flags[i] == 2) {
+    bool mapped = false, refused = false;
+    const bool ref_ok = *ref_status == 0;
+    if (i < ncells && *ref >= 0 && flags[i] == 2 && !ref_ok) {
+        refused = true;
+        if (status) status[i] = 7;
+    } else if (i < ncells && *ref >= 0 && flags[i] == 2) {
         mapped = true;
         // h/R = sum_k Y_k/W_k (a1 T + a2 T^2/2 + a3 T^3/3 + a4 T^4/4 + a5 T^5/5 + a6)
         double Bo[6] = {0, 0, 0, 0, 0, 0}, Bn[6] = {0, 0, 0, 0, 0, 0};
@@ -133,6 +141,8 @@ __global__ __launch_bounds__(MAP_BLOCK) void k_map_scatter(
     }
     const unsigned long long cnt = __ballot(mapped);
     if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(&stats[5], (unsigned long long)__popcll(cnt));
+    const unsigned long long nf = __ballot(refused);
+    if ((threadIdx.x & 63) == 0 && nf) atomicAdd(&stats[3], (unsigned long long)__popcll(nf));
 }
 
 // ------------------------------------------------------------------ queue ---
@@ -147,8 +157,9 @@ __device__ __forceinline__ int cost_bucket(const uint32_t *cost, int64_t i) {
 }
 
 __global__ void k_queue_reset(int *hist, int *cursor, int *seg_ctr, int *n_active,
-                              unsigned long long *stats) {
+                              unsigned long long *stats, int *ref_status) {
     const int t = threadIdx.x;
+    if (t == 0) *ref_status = 0;
     if (t < NBUCKET) { hist[t] = 0; cursor[t] = 0; }
     if (t < NSEG) seg_ctr[t] = 0;
     if (t < 8) stats[t] = 0;
@@ -206,8 +217,9 @@ hipError_t launch_map(int64_t ncells, int N, const double *T, const double *Y, c
 }
 
 hipError_t launch_queue_reset(int *hist, int *cursor, int *seg_ctr, int *n_active,
-                              unsigned long long *stats, hipStream_t s) {
-    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, hist, cursor, seg_ctr, n_active, stats);
+                              unsigned long long *stats, int *ref_status, hipStream_t s) {
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, hist, cursor, seg_ctr, n_active, stats,
+                       ref_status);
     return hipGetLastError();
 }
 
@@ -232,11 +244,12 @@ hipError_t launch_ref_snapshot(int64_t ncells, int N, const double *T, const dou
 hipError_t launch_map_scatter(int64_t ncells, int N, double *T, double *Y, const uint8_t *flags,
                               const int64_t *ref, const double *snap, double *delta,
                               const double *nasa_t, const double *invW, uint8_t *status,
-                              uint32_t *cost, unsigned long long *stats, hipStream_t s) {
+                              uint32_t *cost, unsigned long long *stats, const int *ref_status,
+                              hipStream_t s) {
     hipLaunchKernelGGL(k_ref_delta, dim3(1), dim3(64), 0, s, ncells, N, Y, ref, snap, delta);
     if (ncells > 0)
         hipLaunchKernelGGL(k_map_scatter, dim3(nblk(ncells)), dim3(MAP_BLOCK), 0, s, ncells, N, T, Y,
-                           flags, ref, delta, nasa_t, invW, status, cost, stats);
+                           flags, ref, delta, nasa_t, invW, status, cost, stats, ref_status);
     return hipGetLastError();
 }
 

@@ -147,6 +147,7 @@ struct IntParams {
     int chunk;
     int block_static;       // persistent launch, contiguous block of cells per slot
     unsigned long long *stats;  // [8] device counters
+    int *ref_status;        // nullable: receives the status of the reference cell (flag 1)
 };
 
 }  // namespace chem

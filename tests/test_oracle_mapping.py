@@ -114,3 +114,31 @@ def test_scatter_conserves_enthalpy(o53):
     # zero increment leaves the cell untouched
     T3, Y3 = o53.map_scatter(T, Y, flags, Yref_old, Yref_old)
     np.testing.assert_allclose(T3, T, rtol=1e-15)
+
+
+def test_failed_reference_is_not_copied(o53):
+    """A mapped cell copies the reference's increment only when the
+    reference's integration succeeded: with one attempted step allowed over a
+    long dt the reference stops at the step limit (status 1), and the mapped
+    cells keep their state with status 7; a reference with a bad input state
+    (T <= 0, status 4) does the same."""
+    mech = o53.mech
+    f = synth.field_mapped(2000, seed=31)
+    Yf, Yo = synth.stream_fuel(mech), synth.stream_oxidiser(mech)
+    flags, ref = o53.map_reference(f.T, f.Y, Yf, Yo, 1e-4)
+    mapped = flags == 2
+    assert ref >= 0 and mapped.sum() > 1000
+    T, Y, _, st = o53.step_mapped(f.T, f.p, f.Y, 1e-2, flags, ref, max_steps=1)[:4]
+    assert st[ref] == 1
+    assert np.all(st[mapped] == 7)
+    assert np.array_equal(T[mapped], f.T[mapped]) and np.array_equal(Y[:, mapped], f.Y[:, mapped])
+    # the same field with a normal step maps every candidate (status 5)
+    T, Y, _, st = o53.step_mapped(f.T, f.p, f.Y, 1e-6, flags, ref)[:4]
+    assert st[ref] == 0 and np.all(st[mapped] == 5)
+    assert not np.array_equal(Y[:, mapped], f.Y[:, mapped])
+    # a reference with a bad input state
+    Tb = f.T.copy()
+    Tb[ref] = -1.0
+    T, Y, _, st = o53.step_mapped(Tb, f.p, f.Y, 1e-6, flags, ref)[:4]
+    assert st[ref] == 4 and np.all(st[mapped] == 7)
+    assert np.array_equal(Y[:, mapped], f.Y[:, mapped])
