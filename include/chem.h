@@ -333,6 +333,13 @@ int chem_surrogate_load(chem_ctx *ctx, const char *path);
  * row-major.  dt [n] device.  Kernel-level check of inference. */
 int chem_surrogate_forward(chem_ctx *ctx, int64_t n, const double *T, const double *p,
                            const double *Y, const double *dt, float *out);
+/* The same outputs from the fused inference kernel that
+ * chem_integrate_surrogate runs (the whole network per tile of 64 rows in one
+ * workgroup, activations kept in LDS), every row selected: same arguments and
+ * layout as chem_surrogate_forward.  Its products accumulate in the same
+ * order, so the two entry points agree bit for bit; kernel-level check. */
+int chem_surrogate_forward_fused(chem_ctx *ctx, int64_t n, const double *T, const double *p,
+                                 const double *Y, const double *dt, float *out);
 /* Mean-squared-error loss and its gradient (host, float32, blob layout, the
  * normalisation blocks left at zero) over n pairs (64 <= n <= 65536, n a
  * multiple of 64) with the current parameters and normalisation.

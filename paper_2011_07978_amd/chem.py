@@ -107,6 +107,7 @@ EXPORTS = ["chem_create", "chem_destroy", "chem_set_stream", "chem_last_error",
            "chem_default_train_params", "chem_default_gate_params", "chem_surrogate_param_count",
            "chem_surrogate_train", "chem_surrogate_get_params", "chem_surrogate_set_params",
            "chem_surrogate_save", "chem_surrogate_load", "chem_surrogate_forward",
+           "chem_surrogate_forward_fused",
            "chem_surrogate_loss_grad", "chem_graph_begin", "chem_graph_end", "chem_graph_launch",
            "chem_graph_destroy", "chem_autotune"]
 _VOID = ("chem_destroy", "chem_default_options", "chem_last_error", "chem_default_train_params",
@@ -162,6 +163,7 @@ def load_library(path: str = LIB_PATH):
     L.chem_surrogate_save.argtypes = [vp, C.c_char_p]
     L.chem_surrogate_load.argtypes = [vp, C.c_char_p]
     L.chem_surrogate_forward.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp]
+    L.chem_surrogate_forward_fused.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp]
     L.chem_surrogate_loss_grad.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp, vp,
                                            C.POINTER(C.c_double)]
     L.chem_graph_begin.argtypes = [vp]
@@ -394,6 +396,15 @@ class Chem:
             out = torch.empty((n, 64), dtype=torch.float32, device=T.device)
         self._check(self.L.chem_surrogate_forward(self.h, n, _ptr(T), _ptr(p), _ptr(Y), _ptr(dt),
                                                   _ptr(out)), "chem_surrogate_forward")
+        return out
+
+    def surrogate_forward_fused(self, T, p, Y, dt, out=None):
+        n = T.shape[0]
+        if out is None:
+            out = torch.empty((n, 64), dtype=torch.float32, device=T.device)
+        self._check(self.L.chem_surrogate_forward_fused(self.h, n, _ptr(T), _ptr(p), _ptr(Y),
+                                                        _ptr(dt), _ptr(out)),
+                    "chem_surrogate_forward_fused")
         return out
 
     def surrogate_loss_grad(self, T0, p, Y0, dt, T1, Y1):

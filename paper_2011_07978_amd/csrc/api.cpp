@@ -1082,6 +1082,22 @@ int chem_surrogate_forward(chem_ctx *c, int64_t n, const double *T, const double
     return CHEM_OK;
 }
 
+int chem_surrogate_forward_fused(chem_ctx *c, int64_t n, const double *T, const double *p,
+                                 const double *Y, const double *dt, float *out) {
+    if (!c) return CHEM_E_INVALID_ARG;
+    int rc = check_surrogate(c, true);
+    if (rc) return rc;
+    if (n < 0 || n > (int64_t)INT32_MAX || (n > 0 && (!T || !p || !Y || !dt || !out)))
+        return fail(c, CHEM_E_INVALID_ARG, "chem_surrogate_forward_fused: bad arguments");
+    if (n == 0) return CHEM_OK;
+    if (capturing(c)) return fail(c, CHEM_E_CAPTURE_UNSAFE, "surrogate forward during capture");
+    HIPCHK(c, hipSetDevice(c->device));
+    FeatSrc f{T, p, Y, dt, 0.0, n, c->N};
+    char err[256] = {0};
+    if (c->sur->forward_fused_rows(f, out, c->stream, err)) return fail(c, CHEM_E_HIP, "%s", err);
+    return CHEM_OK;
+}
+
 int chem_surrogate_loss_grad(chem_ctx *c, int64_t n, const double *T0, const double *p,
                              const double *Y0, const double *dt, const double *T1, const double *Y1,
                              float *grad, double *loss) {

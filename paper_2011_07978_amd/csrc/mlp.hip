@@ -644,6 +644,21 @@ __global__ __launch_bounds__(256) void k_mlp_infer(FeatSrc f, int64_t base, int 
 }
 static constexpr size_t kInferLds = sizeof(uint16_t) * (size_t)FT * (XLD + 2 * HLD);
 
+// Every row of a chunk selected, in order (the fused kernel's check entry).
+__global__ __launch_bounds__(256) void k_select_all(int m, int *idx, int *cnt) {
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r < m) idx[r] = r;
+    if (r == 0) *cnt = m;
+}
+
+// out[r][c] = outT[c][r] for a chunk of m rows and 64 outputs
+__global__ __launch_bounds__(256) void k_untranspose(const float *outT, int m, float *out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)m * S_OUT) return;
+    const int r = (int)(i / S_OUT), c = (int)(i % S_OUT);
+    out[i] = outT[(size_t)c * m + r];
+}
+
 static void launch_post(int nel, dim3 g, hipStream_t s, const FeatSrc &f, int64_t base, int m,
                         const float *outT, const PostParams &q, double *T, double *Y, uint8_t *flags,
                         unsigned long long *stats) {
@@ -812,19 +827,24 @@ void Surrogate::colsum(const float *src, int B, int ncol, float *dst, hipStream_
 // few tiles and K (the batch) is long, so the K range is cut into S slices
 // that fill the chip; each slice writes its partial product and a second pass
 // adds the slices in order
-void Surrogate::gemm_wgrad(const uint16_t *A, int lda, const uint16_t *Bm, int ldb, int M, int N,
+bool Surrogate::gemm_wgrad(const uint16_t *A, int lda, const uint16_t *Bm, int ldb, int M, int N,
                            int K, float *C, hipStream_t s) {
     const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
     int S = 1;
     while (tiles * 2 * S <= 256 && K % (64 * S) == 0 && K / (2 * S) >= 128 &&
            (int64_t)2 * S * M * N <= kSplitFloats)
         S *= 2;
+    // launch invariants, checked on the host before anything is enqueued:
+    // every slice is a whole number of 32-wide k steps inside the rows of A
+    // and B, and the S slabs of M x N partial sums fit the slice buffer
+    if (K % S != 0 || (K / S) % 32 != 0 || K > lda || K > ldb || (int64_t)S * M * N > kSplitFloats)
+        return false;
     GemmEpi e{};
     e.ldc = N;
     if (S == 1) {
         e.C = C;
         gemm<EPI_PLAIN>(A, lda, Bm, ldb, M, N, K, e, s);
-        return;
+        return true;
     }
     e.C = kpart;
     hipLaunchKernelGGL(k_gemm_nt<EPI_PLAIN>, dim3((M + 63) / 64, (N + 63) / 64, S), dim3(256), 0, s,
@@ -832,16 +852,21 @@ void Surrogate::gemm_wgrad(const uint16_t *A, int lda, const uint16_t *Bm, int l
     const int64_t mn = (int64_t)M * N;
     hipLaunchKernelGGL(k_sum_slices, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s, kpart, S,
                        mn, C);
+    return true;
 }
 
-// gradients of the mean-squared error for the B rows in X / Tg into G
-void Surrogate::backward(int B, hipStream_t s) {
+// gradients of the mean-squared error for the B rows in X / Tg into G;
+// false (nothing enqueued past the failing launch) if a launch would not fit
+// the workspace
+bool Surrogate::backward(int B, hipStream_t s) {
     const int nout = N + 1;
+    if (B > ws_rows || !ws_training || B % 64 != 0) return false;
     hipLaunchKernelGGL(k_out_grad, dim3((B + 3) / 4), dim3(256), 0, s, out, Tg, B, nout, dOf, dZ5,
                        dZ5T, B, lpart);
     // output layer
     {
-        gemm_wgrad(dZ5T, B, HT[3], B, S_OUT, S_HID, B, G + layer_offset(4), s);   // dW5 = dZ5^T H4
+        if (!gemm_wgrad(dZ5T, B, HT[3], B, S_OUT, S_HID, B, G + layer_offset(4), s))   // dW5 = dZ5^T H4
+            return false;
         colsum(dOf, B, S_OUT, G + layer_offset(4) + (int64_t)S_OUT * S_HID, s);
         GemmEpi e2{};
         e2.C = dH; e2.ldc = S_HID;
@@ -852,7 +877,8 @@ void Surrogate::backward(int B, hipStream_t s) {
                            dZb, dZbT, B, csum);
         const int ni = layer_in(l);
         const uint16_t *inT = l == 0 ? XT : HT[l - 1];
-        gemm_wgrad(dZbT, B, inT, B, S_HID, ni, B, G + layer_offset(l), s);   // dW = dZ^T h_{l-1}
+        if (!gemm_wgrad(dZbT, B, inT, B, S_HID, ni, B, G + layer_offset(l), s))   // dW = dZ^T h_{l-1}
+            return false;
         hipLaunchKernelGGL(k_colsum_final, dim3(1), dim3(256), 0, s, csum, S_HID,
                            G + layer_offset(l) + (int64_t)S_HID * ni);
         if (l > 0) {
@@ -861,6 +887,7 @@ void Surrogate::backward(int B, hipStream_t s) {
             gemm<EPI_PLAIN>(dZb, S_HID, WbT[l], S_HID, B, S_HID, S_HID, e2, s);   // dh = dZ W
         }
     }
+    return true;
 }
 
 int Surrogate::compute_norm(const FeatSrc &f, const TgtSrc &t, hipStream_t s, char *err) {
@@ -959,7 +986,10 @@ int Surrogate::train(const FeatSrc &f, const TgtSrc &t, int epochs, int B, doubl
             hipLaunchKernelGGL(k_build_rows, dim3((B + 3) / 4), dim3(256), 0, s, f, t,
                                d_perm + bi * B, (int64_t)0, B, P + weights_count(), X, XT, B, Tg);
             forward(B, true, false, s);
-            backward(B, s);
+            if (!backward(B, s)) {
+                snprintf(err, 256, "backward: launch does not fit the workspace (batch %d)", B);
+                return -1;
+            }
             const double frac = total > 1 ? (double)step / (double)(total - 1) : 1.0;
             const float lr = (float)(lr1 + 0.5 * (lr0 - lr1) * (1.0 + cos(M_PI * frac)));
             const float b1 = 0.9f, b2 = 0.999f;
@@ -991,7 +1021,10 @@ int Surrogate::loss_grad(const FeatSrc &f, const TgtSrc &t, float *grad_host, do
     hipLaunchKernelGGL(k_build_rows, dim3((B + 3) / 4), dim3(256), 0, s, f, t, (const int *)nullptr,
                        (int64_t)0, B, P + weights_count(), X, XT, B, Tg);
     forward(B, true, false, s);
-    backward(B, s);
+    if (!backward(B, s)) {
+        snprintf(err, 256, "backward: launch does not fit the workspace (%d rows)", B);
+        return -1;
+    }
     hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(256), 0, s, lpart, (B + 3) / 4, d_loss);
     SCHK(hipMemcpyAsync(grad_host, G, sizeof(float) * weights_count(), hipMemcpyDeviceToHost, s));
     double l = 0.0;
@@ -1014,6 +1047,30 @@ int Surrogate::forward_rows(const FeatSrc &f, float *out_dev, hipStream_t s, cha
         forward(m, false, false, s);
         SCHK(hipMemcpyAsync(out_dev + base * S_OUT, out, sizeof(float) * m * S_OUT,
                             hipMemcpyDeviceToDevice, s));
+    }
+    SCHK(hipGetLastError());
+    return 0;
+}
+
+// Raw outputs of the fused inference kernel (the one apply() runs), every row
+// selected, in the row-major layout of forward_rows.
+int Surrogate::forward_fused_rows(const FeatSrc &f, float *out_dev, hipStream_t s, char *err) {
+    const int64_t n = f.n;
+    const int chunk = 262144;
+    int rc = reserve_ws((int)std::min<int64_t>(n, chunk), false, err);
+    if (rc) return rc;
+    MlpW wts{};
+    for (int l = 0; l < 5; ++l) {
+        wts.W[l] = Wb[l];
+        wts.b[l] = P + layer_offset(l) + (int64_t)layer_out(l) * layer_in(l);
+    }
+    for (int64_t base = 0; base < n; base += chunk) {
+        const int m = (int)std::min<int64_t>(chunk, n - base);
+        hipLaunchKernelGGL(k_select_all, dim3((m + 255) / 256), dim3(256), 0, s, m, idx, sel_cnt);
+        hipLaunchKernelGGL(k_mlp_infer, dim3((m + FT - 1) / FT), dim3(256), kInferLds, s, f, base, m,
+                           idx, sel_cnt, P + weights_count(), wts, out);
+        hipLaunchKernelGGL(k_untranspose, dim3((unsigned)(((int64_t)m * S_OUT + 255) / 256)), dim3(256),
+                           0, s, out, m, out_dev + base * S_OUT);
     }
     SCHK(hipGetLastError());
     return 0;

@@ -67,9 +67,9 @@ struct Surrogate {
     int get_params(float *host, hipStream_t s, char *err);
     int reserve_ws(int rows, bool training, char *err);
     void forward(int B, bool training, bool out_transposed, hipStream_t s);
-    void backward(int B, hipStream_t s);
+    bool backward(int B, hipStream_t s);
     void colsum(const float *src, int B, int ncol, float *dst, hipStream_t s);
-    void gemm_wgrad(const uint16_t *A, int lda, const uint16_t *Bm, int ldb, int M, int N, int K,
+    bool gemm_wgrad(const uint16_t *A, int lda, const uint16_t *Bm, int ldb, int M, int N, int K,
                     float *C, hipStream_t s);
     int compute_norm(const FeatSrc &f, const TgtSrc &t, hipStream_t s, char *err);
     int train(const FeatSrc &f, const TgtSrc &t, int epochs, int B, double lr0, double lr1,
@@ -77,6 +77,7 @@ struct Surrogate {
     int loss_grad(const FeatSrc &f, const TgtSrc &t, float *grad_host, double *loss, hipStream_t s,
                   char *err);
     int forward_rows(const FeatSrc &f, float *out_dev, hipStream_t s, char *err);
+    int forward_fused_rows(const FeatSrc &f, float *out_dev, hipStream_t s, char *err);
     int apply(const FeatSrc &f, double *T, double *Y, uint8_t *flags, const PostIn &pin,
               unsigned long long *stats, hipStream_t s, char *err);
 };

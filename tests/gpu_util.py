@@ -62,3 +62,73 @@ def compare_to_oracle(out, ref_T, ref_Y, nacc_ref=None, nrej_ref=None, rtol_T=1e
         rep["step_sequence_differs"] = int((~same).sum())
     rep["ok"] = rep["max_rel_T"] <= rtol_T and rep["max_abs_Y"] <= atol_Y
     return rep
+
+
+RU_ERG = 8.314462618e7
+EPS = 2.0 ** -52
+
+
+def rounding_scale(o, mech, T, p, Y):
+    """Per-component rounding scale of f = (dT/dt, dY_k/dt) for a log-space
+    rate evaluation.  Each gross rate m_j k Pi C (forward and reverse; m_j the
+    third-body concentration, or the fall-off factor G) is the exponential of
+    a sum whose terms reach |ln k_f| + |ln K_c| + ~64 in size, so it carries a
+    relative error of about eps times that.  Species k collects
+    sum_j |nu_kj| of those errors, times W_k / rho; dT/dt collects the
+    species' errors weighted by |H_k / W_k| / cp.  Returns that scale [n]."""
+    N, R = mech.n_species, mech.n_reactions
+    kf, kr, q, _ = o.kinetics(T, p, Y)
+    rho = o.density(T, p, Y)
+    C = rho * Y / mech.W
+    m = np.ones(R)
+    tb = mech.third_body != 0
+    m[tb] = C.sum()
+    for j, k, a in zip(mech.eff_reaction, mech.eff_species, mech.eff_value):
+        m[j] += (a - 1.0) * C[k]
+    fo = getattr(mech, "falloff", None)
+    if fo is not None:
+        for j in np.nonzero(fo)[0]:
+            m[j] = o.falloff_factor(j, T, m[j])
+    Cx = np.r_[C, 1.0]
+    gross = m * (kf * Cx[mech.reactants].prod(axis=1) + kr * Cx[mech.products].prod(axis=1))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        lsize = np.abs(np.log(kf)) + np.abs(np.log(kf) - np.log(kr))
+    lsize = np.nan_to_num(lsize, nan=0.0, posinf=0.0) + 64.0
+    err = np.zeros(N)
+    for side in (mech.reactants, mech.products):
+        for col in side.T:
+            ok = col >= 0
+            np.add.at(err, col[ok], (gross * lsize)[ok])
+    err *= mech.W / rho * EPS
+    _, hRT, _ = o.thermo(T)
+    hw = np.abs(RU_ERG * T * hRT / mech.W) / o.cp(T, Y)
+    return np.r_[hw @ err, err]
+
+
+def check_rhs_jac(o, mech, field, f, J, label):
+    """f [n, nn] and J [n, nn, nn] of the kernels against the oracle's RHS and
+    complex-step Jacobian, per component: f_r within 100 of its rounding
+    scale; the Jacobian's species columns scaled by their own mass fraction,
+    J_rc |Y_c|, within 1000 of row r's rounding scale (a derivative with
+    respect to ln C_c of a gross rate is at most its order times the rate);
+    and every entry within 1e-12 of its row's largest entry (the temperature
+    column, and species absent from the cell, whose scaled column is zero)."""
+    worst_f = worst_Jc = worst_Jr = 0.0
+    for i in range(field.n_cells):
+        y = np.concatenate([[field.T[i]], field.Y[:, i]])
+        fo = o.rhs(field.p[i], y)
+        Jo = o.jac_cs(field.p[i], y)
+        sc = rounding_scale(o, mech, field.T[i], field.p[i], field.Y[:, i])
+        # a species in no reaction has a zero scale: its rate must be exactly zero
+        ratio = lambda d, s: np.where(s > 0, d / np.where(s > 0, s, 1.0), np.where(d > 0, np.inf, 0.0))
+        worst_f = max(worst_f, float(ratio(np.abs(f[i] - fo), sc).max()))
+        dJ = np.abs(J[i] - Jo)
+        worst_Jc = max(worst_Jc, float(ratio(dJ[:, 1:] * np.abs(y[1:])[None, :], sc[:, None]).max()))
+        rows = np.abs(Jo).max(axis=1)
+        rows = np.where(rows > 0, rows, 1.0)
+        worst_Jr = max(worst_Jr, float((dJ.max(axis=1) / rows).max()))
+    print(f"{label}: f {worst_f:.3g} of its rounding scale; J column-scaled {worst_Jc:.3g} of it; "
+          f"J row-relative {worst_Jr:.3g}", flush=True)
+    assert worst_f <= 100.0, worst_f
+    assert worst_Jc <= 1000.0, worst_Jc
+    assert worst_Jr <= 1e-12, worst_Jr

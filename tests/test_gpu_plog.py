@@ -53,20 +53,8 @@ def test_rhs_and_jacobian_with_plog(name):
     torch.cuda.synchronize()
     fd = host(fd).reshape(n, nn)
     J = host(J).reshape(n, nn, nn)
-    worst_f = worst_J = 0.0
-    for i in range(n):
-        y = np.concatenate([[f.T[i]], f.Y[:, i]])
-        fo = o.rhs(f.p[i], y)
-        Jo = o.jac_cs(f.p[i], y)
-        sf = np.abs(fo[1:]).max()
-        worst_f = max(worst_f, abs(fd[i, 0] - fo[0]) / max(abs(fo[0]), 1e-300),
-                      np.abs(fd[i, 1:] - fo[1:]).max() / max(sf, 1e-300))
-        rows = np.abs(Jo).max(axis=1)
-        rows = np.where(rows > 0, rows, 1.0)
-        worst_J = max(worst_J, float((np.abs(J[i] - Jo).max(axis=1) / rows).max()))
-    print(name, "worst rhs", worst_f, "worst jac", worst_J)
-    assert worst_f <= 1e-10, worst_f
-    assert worst_J <= 1e-10, worst_J
+    from tests.gpu_util import check_rhs_jac
+    check_rhs_jac(o, mech, f, fd, J, "plog " + name)
 
 
 @pytest.mark.parametrize("name", MECHS)

@@ -249,9 +249,9 @@ def test_training_reduces_loss_and_roundtrips():
     c = chem_for(mech)
     pairs = surrogate.generate_pairs(c, n_cells=16384, n_steps=2, seed=71)
     assert pairs.n >= 30000
-    hist = surrogate.train(c, pairs, epochs=4, batch=1024, seed=72)
+    hist = surrogate.train(c, pairs, epochs=8, batch=1024, seed=72)
     print("loss history", hist)
-    assert np.all(np.isfinite(hist)) and hist[-1] < 0.75 * hist[0]
+    assert np.all(np.isfinite(hist)) and hist[-1] < 0.5 * hist[0]
     P = c.surrogate_get_params()
     assert np.all(np.isfinite(P))
     sub = pairs.take(np.arange(700))
