@@ -292,6 +292,23 @@ int chem_integrate(chem_ctx *ctx, int64_t n_cells, double *T, const double *p, d
                    double dt, const uint8_t *flags, const int64_t *ref_index, double *h,
                    uint32_t *cost, uint8_t *status, int32_t *steps, chem_stats *stats);
 
+/* chem_integrate for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, hosts that forbid allocation): the
+ * same arguments, kernels and results, but the call allocates nothing.  Its
+ * scratch (heavy-first queue, counters, statistics, the reference cell's
+ * snapshot and increment) is a fixed device array inside the library, one
+ * per device, 8 MiB + 8 KiB, held until the process ends; the caller passes
+ * the state, as for chem_integrate.  Limits: n_cells <= 2097152 (larger n
+ * returns CHEM_E_INVALID_ARG, nothing enqueued), mechanisms of up to 63
+ * species (the wavefront integrator; larger ones return CHEM_E_UNIMPL).
+ * Every call on a device shares that device's array and re-initialises what
+ * it reads; calls that overlap in time on one device (several contexts or
+ * streams) race and must be serialised by the caller.  A context must exist
+ * on the device (chem_create resolves the array's device address there). */
+int chem_integrate_noalloc(chem_ctx *ctx, int64_t n_cells, double *T, const double *p, double *Y,
+                           double dt, const uint8_t *flags, const int64_t *ref_index, double *h,
+                           uint32_t *cost, uint8_t *status, int32_t *steps, chem_stats *stats);
+
 /* chem_integrate with the learned surrogate first: every cell whose flag is
  * CHEM_FLAG_SOLVE is offered to the surrogate; cells the gate accepts are
  * updated in place and flagged CHEM_FLAG_SURROGATE (flags is device in/out

@@ -101,7 +101,7 @@ class TuneEntry(C.Structure):
 
 EXPORTS = ["chem_create", "chem_destroy", "chem_set_stream", "chem_last_error",
            "chem_set_mechanism", "chem_validate_mechanism", "chem_max_species", "chem_set_options", "chem_get_options",
-           "chem_query_slots", "chem_plan_balance",
+           "chem_query_slots", "chem_plan_balance", "chem_integrate_noalloc",
            "chem_default_options", "chem_reserve", "chem_map_reference", "chem_integrate",
            "chem_eval_rhs_jac", "chem_rodas_step", "chem_integrate_surrogate",
            "chem_default_train_params", "chem_default_gate_params", "chem_surrogate_param_count",
@@ -146,6 +146,7 @@ def load_library(path: str = LIB_PATH):
     L.chem_map_reference.argtypes = [vp, C.c_int64, vp, vp, vp, C.POINTER(MapParams), vp, vp]
     L.chem_integrate.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_double, vp, vp, vp, vp, vp, vp,
                                  C.POINTER(Stats)]
+    L.chem_integrate_noalloc.argtypes = L.chem_integrate.argtypes
     L.chem_eval_rhs_jac.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp]
     L.chem_rodas_step.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_double, vp, vp]
     L.chem_integrate_surrogate.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_double, vp, vp,
@@ -315,6 +316,19 @@ class Chem:
         self._check(self.L.chem_map_reference(self.h, n, _ptr(T), _ptr(p), _ptr(Y), C.byref(mp),
                                               _ptr(flags), _ptr(ref_index)), "chem_map_reference")
         return flags, ref_index
+
+    def integrate_noalloc(self, T, p, Y, dt, flags=None, ref_index=None, h=None, cost=None,
+                          status=None, steps=None, stats=False):
+        """chem_integrate_noalloc: chem_integrate with the library's fixed
+        device workspace (no allocation; at most 2097152 cells)."""
+        n = T.shape[0]
+        st = Stats() if stats else None
+        rc = self.L.chem_integrate_noalloc(self.h, n, _ptr(T), _ptr(p), _ptr(Y), float(dt),
+                                           _ptr(flags), _ptr(ref_index), _ptr(h), _ptr(cost),
+                                           _ptr(status), _ptr(steps),
+                                           C.byref(st) if st is not None else None)
+        self._check(rc, "chem_integrate_noalloc")
+        return st.as_dict() if st is not None else None
 
     def integrate(self, T, p, Y, dt, flags=None, ref_index=None, h=None, cost=None,
                   status=None, steps=None, stats=False):

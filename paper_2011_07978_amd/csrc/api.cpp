@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -116,6 +117,51 @@ static bool capturing(chem_ctx *c) {
     return st != hipStreamCaptureStatusNone;
 }
 
+// ---- fixed workspace of chem_integrate_noalloc ----------------------------
+// For callers that cannot allocate, the integration's per-call scratch lives
+// in a fixed device array of this library's code object: every device the
+// library runs on holds its own copy until the process ends.  Layout (bytes):
+// [0, 320) queue counters (32 bucket offsets, 32 cursors, 8 segment counters,
+// the active count at int 72, the reference cell's status at int 76),
+// [512, 576) call statistics (8 x u64), [1024, 2312) the reference cell's
+// state before the step (<= 161 doubles), [2560, 3840) its increment
+// (<= 160 doubles), [4096, 4104) the "no reference cell" index (-1), and from
+// 8192 the heavy-first queue (int32 per cell).  Calls that overlap on one
+// device share it and race; every call re-initialises what it reads.
+constexpr int64_t kNoAllocMaxCells = (int64_t)1 << 21;
+constexpr size_t kScrStats = 512, kScrSnap = 1024, kScrDelta = 2560, kScrNone = 4096,
+                 kScrQueue = 8192;
+constexpr size_t kScratchBytes = kScrQueue + sizeof(int) * (size_t)kNoAllocMaxCells;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// Device address of `scratch` on each device, resolved once per device by
+// chem_create with that device current.  In host code the array's name is
+// only a stand-in: kernels and copies must use these addresses.
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static unsigned char *g_scratch_dev[kMaxDevices];
+
+static hipError_t resolve_scratch(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    if (g_scratch_dev[device]) return hipSuccess;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_dev[device] = (unsigned char *)ptr;
+    return hipSuccess;
+}
+
+static unsigned char *scratch_on(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return device >= 0 && device < kMaxDevices ? g_scratch_dev[device] : nullptr;
+}
+
+__global__ void k_set_i64(int64_t *p, int64_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
 // Exported functions take C linkage from their declarations in chem.h.
 
 void chem_default_options(chem_options *o) {
@@ -151,7 +197,8 @@ int chem_create(chem_ctx **out, int hip_device, void *hip_stream) {
         hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
         hipEventCreate(&c->ev2) != hipSuccess || hipEventCreate(&c->ev3) != hipSuccess ||
         hipEventCreate(&c->ev4) != hipSuccess || hipEventCreate(&c->ev5) != hipSuccess ||
-        hipMalloc((void **)&c->d_refnone, sizeof(int64_t)) != hipSuccess) {
+        hipMalloc((void **)&c->d_refnone, sizeof(int64_t)) != hipSuccess ||
+        resolve_scratch(hip_device) != hipSuccess) {
         chem_destroy(c);
         return CHEM_E_HIP;
     }
@@ -820,17 +867,33 @@ static int check_integrator(chem_ctx *c) {
 
 // One call of the hot path: optional surrogate pass over flag-0 cells, work
 // queue, Rosenbrock integration of the remaining cells, mapped-cell scatter.
+// Per-call scratch of one integration call: the context's buffers (which the
+// queue may grow) or the fixed array of chem_integrate_noalloc.
+struct CallWork {
+    int *queue;
+    int *small;                  // hist[32] cursor[32] seg[8] n_active (72), ref status (76)
+    unsigned long long *stats;   // [8]
+    double *snap, *delta;        // reference state before the step, its increment
+    int64_t *refnone;            // device -1
+    bool fixed;                  // true: no allocation; nothing may grow
+};
+
+static CallWork ctx_work(chem_ctx *c) {
+    return CallWork{c->d_queue, c->d_small, c->d_stats, c->d_snap, c->d_delta, c->d_refnone, false};
+}
+
 static int integrate_core(chem_ctx *c, int64_t n, double *T, const double *p, double *Y, double dt,
                           uint8_t *flags, const int64_t *ref_index, double *h, uint32_t *cost,
                           uint8_t *status, int32_t *steps, chem_stats *stats,
-                          const chem_gate_params *gate) {
+                          const chem_gate_params *gate, CallWork w) {
     int rc = check_integrator(c);
     if (rc) return rc;
     HIPCHK(c, hipSetDevice(c->device));
     const bool cap = capturing(c);
     if (stats && cap) return fail(c, CHEM_E_CAPTURE_UNSAFE, "stats requested during capture");
-    if (c->opt.schedule == CHEM_SCHED_QUEUE && n > c->cap) {
+    if (!w.fixed && c->opt.schedule == CHEM_SCHED_QUEUE && n > c->cap) {
         if ((rc = chem_reserve(c, n))) return rc;
+        w.queue = c->d_queue;
     }
     if (gate && n > 0) {
         if (!c->sur || !c->sur->trained)
@@ -839,12 +902,18 @@ static int integrate_core(chem_ctx *c, int64_t n, double *T, const double *p, do
         if (c->sur->ws_rows < (int)std::min<int64_t>(n, 262144) && cap)
             return fail(c, CHEM_E_CAPTURE_UNSAFE, "surrogate workspace growth during capture");
     }
-    if (!ref_index) ref_index = c->d_refnone;
     hipStream_t s = c->stream;
+    if (!ref_index) {
+        ref_index = w.refnone;
+        if (w.fixed) {
+            hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(64), 0, s, w.refnone, (int64_t)-1);
+            HIPCHK(c, hipGetLastError());
+        }
+    }
     if (stats) HIPCHK(c, hipEventRecord(c->ev0, s));
-    int *hist = c->d_small, *cursor = c->d_small + 32, *seg = c->d_small + 64, *nact = c->d_small + 72;
-    int *ref_status = c->d_small + 76;
-    HIPCHK(c, launch_queue_reset(hist, cursor, seg, nact, c->d_stats, ref_status, s));
+    int *hist = w.small, *cursor = w.small + 32, *seg = w.small + 64, *nact = w.small + 72;
+    int *ref_status = w.small + 76;
+    HIPCHK(c, launch_queue_reset(hist, cursor, seg, nact, w.stats, ref_status, s));
     if (n > 0) {
         if (gate) {
             if (stats) HIPCHK(c, hipEventRecord(c->ev4, s));
@@ -852,11 +921,11 @@ static int integrate_core(chem_ctx *c, int64_t n, double *T, const double *p, do
             PostIn pin{c->M.nasa_t, c->M.invW, gate->tau_T, gate->y_min, gate->margin, gate->max_dT,
                        gate->T_max};
             char err[256] = {0};
-            if (c->sur->apply(f, T, Y, flags, pin, c->d_stats, s, err))
+            if (c->sur->apply(f, T, Y, flags, pin, w.stats, s, err))
                 return fail(c, CHEM_E_HIP, "surrogate: %s", err);
             if (stats) HIPCHK(c, hipEventRecord(c->ev5, s));
         }
-        if (flags) HIPCHK(c, launch_ref_snapshot(n, c->N, T, Y, ref_index, c->d_snap, s));
+        if (flags) HIPCHK(c, launch_ref_snapshot(n, c->N, T, Y, ref_index, w.snap, s));
         IntParams P{};
         P.rtol = c->opt.rtol;
         P.atol = c->opt.atol;
@@ -866,7 +935,7 @@ static int integrate_core(chem_ctx *c, int64_t n, double *T, const double *p, do
         P.ncells = n;
         P.T = T; P.p = p; P.Y = Y; P.h = h; P.cost = cost; P.status = status; P.steps = steps;
         P.flags = flags;
-        P.stats = c->d_stats;
+        P.stats = w.stats;
         P.ref_status = ref_status;
         int grid = 0;
         if (c->big) {
@@ -875,8 +944,8 @@ static int integrate_core(chem_ctx *c, int64_t n, double *T, const double *p, do
         }
         if (c->opt.schedule == CHEM_SCHED_QUEUE) {
             HIPCHK(c, launch_queue_build(n, flags, c->opt.order_by_cost ? cost : nullptr, hist, cursor,
-                                         nact, c->d_queue, s));
-            P.queue = c->d_queue;
+                                         nact, w.queue, s));
+            P.queue = w.queue;
             P.seg_ctr = seg;
             P.n_active = nact;
             P.chunk = c->opt.queue_chunk > 0 ? c->opt.queue_chunk : 1;
@@ -900,13 +969,13 @@ static int integrate_core(chem_ctx *c, int64_t n, double *T, const double *p, do
             HIPCHK(c, launch_integrate(c->NP, c->M, c->d_mech, P, c->opt.schedule, grid, s));
         if (stats) HIPCHK(c, hipEventRecord(c->ev3, s));
         if (flags)
-            HIPCHK(c, launch_map_scatter(n, c->N, T, Y, flags, ref_index, c->d_snap, c->d_delta,
-                                         c->M.nasa_t, c->M.invW, status, cost, c->d_stats,
+            HIPCHK(c, launch_map_scatter(n, c->N, T, Y, flags, ref_index, w.snap, w.delta,
+                                         c->M.nasa_t, c->M.invW, status, cost, w.stats,
                                          ref_status, s));
     }
     if (!stats) return CHEM_OK;
     HIPCHK(c, hipEventRecord(c->ev1, s));
-    HIPCHK(c, hipMemcpyAsync(c->h_stats, c->d_stats, 8 * sizeof(unsigned long long),
+    HIPCHK(c, hipMemcpyAsync(c->h_stats, w.stats, 8 * sizeof(unsigned long long),
                              hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     float ms = 0.0f, msi = 0.0f, mss = 0.0f;
@@ -937,7 +1006,31 @@ int chem_integrate(chem_ctx *c, int64_t n, double *T, const double *p, double *Y
     if (n > 0 && (!T || !p || !Y)) return fail(c, CHEM_E_INVALID_ARG, "null state array");
     if (flags && !ref_index) return fail(c, CHEM_E_INVALID_ARG, "flags need ref_index");
     return integrate_core(c, n, T, p, Y, dt, const_cast<uint8_t *>(flags), ref_index, h, cost, status,
-                          steps, stats, nullptr);
+                          steps, stats, nullptr, ctx_work(c));
+}
+
+int chem_integrate_noalloc(chem_ctx *c, int64_t n, double *T, const double *p, double *Y, double dt,
+                           const uint8_t *flags, const int64_t *ref_index, double *h, uint32_t *cost,
+                           uint8_t *status, int32_t *steps, chem_stats *stats) {
+    if (!c) return CHEM_E_INVALID_ARG;
+    if (n < 0 || n > kNoAllocMaxCells || !(dt > 0.0) || !isfinite(dt))
+        return fail(c, CHEM_E_INVALID_ARG,
+                    "chem_integrate_noalloc: n = %lld outside [0, %lld] (the fixed workspace's "
+                    "capacity) or bad dt", (long long)n, (long long)kNoAllocMaxCells);
+    if (n > 0 && (!T || !p || !Y)) return fail(c, CHEM_E_INVALID_ARG, "null state array");
+    if (flags && !ref_index) return fail(c, CHEM_E_INVALID_ARG, "flags need ref_index");
+    if (c->has_mech && c->big)
+        return fail(c, CHEM_E_UNIMPL, "chem_integrate_noalloc: mechanisms above 63 species need "
+                                      "Jacobian slots sized to the device; use chem_integrate");
+    if (c->has_mech && c->N + 1 > (int)((kScrDelta - kScrSnap) / sizeof(double)))
+        return fail(c, CHEM_E_UNIMPL, "chem_integrate_noalloc: too many species for the fixed workspace");
+    unsigned char *base = scratch_on(c->device);
+    if (!base) return fail(c, CHEM_E_HIP, "chem_integrate_noalloc: workspace address not resolved");
+    CallWork w{(int *)(base + kScrQueue), (int *)base, (unsigned long long *)(base + kScrStats),
+               (double *)(base + kScrSnap), (double *)(base + kScrDelta), (int64_t *)(base + kScrNone),
+               true};
+    return integrate_core(c, n, T, p, Y, dt, const_cast<uint8_t *>(flags), ref_index, h, cost, status,
+                          steps, stats, nullptr, w);
 }
 
 int chem_integrate_surrogate(chem_ctx *c, int64_t n, double *T, const double *p, double *Y,
@@ -951,7 +1044,8 @@ int chem_integrate_surrogate(chem_ctx *c, int64_t n, double *T, const double *p,
     if (!(gate->tau_T >= 0.0) || !(gate->margin >= 0.0) || gate->y_min != gate->y_min ||
         !(gate->max_dT >= 0.0) || gate->T_max != gate->T_max)
         return fail(c, CHEM_E_INVALID_ARG, "bad gate parameters");
-    return integrate_core(c, n, T, p, Y, dt, flags, ref_index, h, cost, status, steps, stats, gate);
+    return integrate_core(c, n, T, p, Y, dt, flags, ref_index, h, cost, status, steps, stats, gate,
+                          ctx_work(c));
 }
 
 // ------------------------------------------------------------ surrogate ----
@@ -1260,7 +1354,8 @@ int chem_autotune(chem_ctx *c, int64_t n, const double *T, const double *p, cons
     // one untimed pass records the per-cell cost that orders the queue
     hipError_t e = fresh(nullptr);
     if (e != hipSuccess) { release(); return fail(c, CHEM_E_HIP, "autotune copy: %s", hipGetErrorString(e)); }
-    rc = integrate_core(c, n, dT, p, dY, dt, fl, ref_index, dh, dcost, nullptr, nullptr, &st, nullptr);
+    rc = integrate_core(c, n, dT, p, dY, dt, fl, ref_index, dh, dcost, nullptr, nullptr, &st, nullptr,
+                        ctx_work(c));
     if (rc < 0) { release(); return rc; }
     e = hipMemcpyAsync(dcost0, dcost, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) { release(); return fail(c, CHEM_E_HIP, "autotune copy: %s", hipGetErrorString(e)); }
@@ -1283,7 +1378,8 @@ int chem_autotune(chem_ctx *c, int64_t n, const double *T, const double *p, cons
             release();
             return fail(c, CHEM_E_HIP, "autotune copy: %s", hipGetErrorString(e));
         }
-        rc = integrate_core(c, n, dT, p, dY, dt, fl, ref_index, dh, dcost, nullptr, nullptr, &st, nullptr);
+        rc = integrate_core(c, n, dT, p, dY, dt, fl, ref_index, dh, dcost, nullptr, nullptr, &st, nullptr,
+                        ctx_work(c));
         if (rc < 0) { c->opt = saved; release(); return rc; }
         if (k < max_res) res[k] = chem_tune_entry{cd.sched, cd.chunk, cd.slots, st.ms_total};
         ++k;
