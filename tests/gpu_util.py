@@ -107,12 +107,14 @@ def rounding_scale(o, mech, T, p, Y):
 
 def check_rhs_jac(o, mech, field, f, J, label):
     """f [n, nn] and J [n, nn, nn] of the kernels against the oracle's RHS and
-    complex-step Jacobian, per component: f_r within 100 of its rounding
+    complex-step Jacobian, per component: f_r within 20 of its rounding
     scale; the Jacobian's species columns scaled by their own mass fraction,
-    J_rc |Y_c|, within 1000 of row r's rounding scale (a derivative with
+    J_rc |Y_c|, within 20 of row r's rounding scale (a derivative with
     respect to ln C_c of a gross rate is at most its order times the rate);
-    and every entry within 1e-12 of its row's largest entry (the temperature
-    column, and species absent from the cell, whose scaled column is zero)."""
+    and every entry within 5e-13 of its row's largest entry (the temperature
+    column, and species absent from the cell, whose scaled column is zero).
+    On gfx950 the worst cells reach about 2.5 of the scale and 6e-14 of the
+    row, so the bounds leave a factor of about 8."""
     worst_f = worst_Jc = worst_Jr = 0.0
     for i in range(field.n_cells):
         y = np.concatenate([[field.T[i]], field.Y[:, i]])
@@ -129,6 +131,6 @@ def check_rhs_jac(o, mech, field, f, J, label):
         worst_Jr = max(worst_Jr, float((dJ.max(axis=1) / rows).max()))
     print(f"{label}: f {worst_f:.3g} of its rounding scale; J column-scaled {worst_Jc:.3g} of it; "
           f"J row-relative {worst_Jr:.3g}", flush=True)
-    assert worst_f <= 100.0, worst_f
-    assert worst_Jc <= 1000.0, worst_Jc
-    assert worst_Jr <= 1e-12, worst_Jr
+    assert worst_f <= 20.0, worst_f
+    assert worst_Jc <= 20.0, worst_Jc
+    assert worst_Jr <= 5e-13, worst_Jr

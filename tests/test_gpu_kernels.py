@@ -57,10 +57,12 @@ def test_single_rodas_step_matches_oracle(name, field):
             if not np.all(np.isfinite(yo)):
                 continue
             # one step solves six systems with M = I/(gamma h) - J; a backward-
-            # stable solve has a forward error of about cond(M) eps, and the two
-            # sides' six solves, stage sums and RHS roundings add up to the 20
+            # stable solve has a forward error of at most about cond(M) eps
+            # (growth factor ~1 with partial pivoting), once on each side; the
+            # 4 covers the two sides and the stage sums (worst cells measured
+            # at 0.2 of this bound)
             Mo = np.eye(nn) / (0.25 * hstep) - o.jac(field.p[i], y)
-            bound = max(1e-12, 20 * 2.2e-16 * np.linalg.cond(Mo))
+            bound = max(1e-12, 4 * 2.2e-16 * np.linalg.cond(Mo))
             scale = np.abs(y) + np.abs(yo) + 1e-12
             r_y = np.max(np.abs(yn[i] - yo) / scale) / bound
             # the error estimate is the last stage's solution: per component, to

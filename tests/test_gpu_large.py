@@ -67,7 +67,7 @@ def test_single_rodas_step_matches_oracle(mech):
             if not np.all(np.isfinite(yo)):
                 continue
             Mo = np.eye(nn) / (0.25 * hstep) - o.jac(f.p[i], y)
-            bound = max(1e-12, 20 * 2.2e-16 * np.linalg.cond(Mo))
+            bound = max(1e-12, 4 * 2.2e-16 * np.linalg.cond(Mo))
             scale = np.abs(y) + np.abs(yo) + 1e-12
             r_y = np.max(np.abs(yn[i] - yo) / scale) / bound
             r_e = np.max(np.abs(er[i] - eo) / scale) / bound

@@ -60,8 +60,10 @@ def test_forward_matches_bf16_oracle():
     print("forward: max", err.max() / scale, "median", np.median(err) / scale,
           "bf16 effect", np.abs(exact - emu)[:, live].mean() / scale)
     assert np.all(out[:, N + 1:] == 0.0)           # padded outputs: zero rows, zero bias
-    assert err.max() <= 1e-2 * scale
-    assert np.median(err) <= 2e-4 * scale
+    # FP32 accumulation against FP64: differences far below a bfloat16 ulp,
+    # except where that changes the rounding of an activation to bfloat16
+    assert err.max() <= 5e-3 * scale
+    assert np.median(err) <= 1e-7 * scale
     # the kernel rounds like the emulation, not like FP64
     assert err.mean() < 0.25 * np.abs(exact - emu)[:, live].mean()
 

@@ -25,10 +25,12 @@ N_CELLS = CHUNK + 1000
 
 
 def _live_params(N, seed):
-    """Random weights in every layer; the output bias sets increments of
-    about 1e-7 per species and 0.2 K, the live output weights spread them by
-    a factor of about e^(+-0.5) from cell to cell."""
-    return synth.surrogate_params(N, seed=seed, out_sd=(1.0, 1.0),
+    """Random weights in every layer, 1.5 times the 1/sqrt(fan-in) scale so
+    that the network's output varies from cell to cell (the temperature
+    output by about 0.7 in the inverse-sinh scale: predicted increments from
+    about 1.5 K to 20 K); the output bias centres the increments at about
+    1e-7 per species and 0.2 K."""
+    return synth.surrogate_params(N, seed=seed, weight_scale=1.5, out_sd=(1.0, 1.0),
                                   out_bias=synth.surrogate_increment_bias(N, seed + 1, 1e-7, 0.2))
 
 
@@ -69,7 +71,7 @@ def test_fused_inference_equals_layer_path():
     got = b[torch.as_tensor(idx, device="cuda")].cpu().numpy()
     err = np.abs(got[:, :N + 1] - emu[:, :N + 1])
     print("fused vs oracle: max", err.max(), "median", np.median(err))
-    assert np.median(err) <= 2e-3 and err.max() <= 5e-2
+    assert np.median(err) <= 1e-6 and err.max() <= 5e-3
 
 
 def test_live_weights_gate_and_states_match_oracle():
@@ -102,11 +104,14 @@ def test_live_weights_gate_and_states_match_oracle():
     ok_o = np.array([r[0] for r in res])
     T_o = np.array([r[1] for r in res])
     Y_o = np.stack([r[2] for r in res], axis=1)
-    # the network's rounding band: GPU and oracle outputs differ by a few
-    # bfloat16 roundings of activations, well under 2 % of the increment
-    marginal = np.abs(gaps - tau) <= 2e-2 * tau
+    # the network's rounding band: GPU and oracle outputs differ where an
+    # activation rounds to the other neighbouring bfloat16 value; the whole
+    # bfloat16 effect (emulation against FP64) moves the temperature output by
+    # under 0.04 in the inverse-sinh scale, i.e. under 4 % of the increment
+    marginal = np.abs(gaps - tau) <= 5e-2 * tau
     print("oracle accepts", ok_o.sum(), "of", idx.size, "sampled; marginal", marginal.sum())
     assert 0.3 * idx.size < ok_o.sum() < 0.7 * idx.size
+    assert marginal.sum() <= 0.4 * idx.size     # most decisions are compared exactly
     say("surrogate live weights", n, "cells, tau", tau)
     c = chem_for(mech)
     c.surrogate_set_params(P)
@@ -130,8 +135,8 @@ def test_live_weights_gate_and_states_match_oracle():
     eY = np.abs(Yg[:, both] - Y_o[:, both]).max(axis=0)
     print("accepted states: max |dT err| / |dT|", (eT / dT_o).max(),
           "max |dY err| / max|dY|", (eY / dY_o).max())
-    assert np.all(eT <= 2e-2 * dT_o + 1e-9)
-    assert np.all(eY <= 2e-2 * dY_o + 1e-15)
+    assert np.all(eT <= 5e-2 * dT_o + 1e-9)
+    assert np.all(eY <= 5e-2 * dY_o + 1e-15)
     E = mech.composition.T / mech.W[None, :]
     assert np.abs(E @ (Yg[:, acc] - f.Y[:, idx][:, acc])).max() <= 1e-15
     # the sample covers both chunks and the ragged tail
