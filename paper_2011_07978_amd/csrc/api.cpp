@@ -720,7 +720,6 @@ int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
     }
     // LDS layout (doubles)
     int off = 0;
-    M.off_J = off; off += M.n * M.ldj;
     M.off_q = off; off += N + 1;   // production rates (+ sentinel)
     M.off_C = off; off += N + 1;
     M.off_g = off; off += N + 1;

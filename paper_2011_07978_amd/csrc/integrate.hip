@@ -18,6 +18,14 @@
 //   - triangular solves follow the same layout.
 // The cell's arithmetic does not depend on which workgroup runs it, so the
 // static launch and the work-queue launch give bit-identical results.
+//
+// LDS of a work-queue workgroup: the shared species and reaction records,
+// one small region per wavefront (concentrations, Gibbs energies, production
+// rates, solve results), and a pool of Jacobian slots smaller than the number
+// of wavefronts.  A wavefront holds a slot only from the Jacobian's assembly
+// until the iteration matrix has been built in its registers; after a
+// rejected step it assembles the (identical) Jacobian again.  This keeps
+// eight wavefronts, two per SIMD, on a CU for the 53-species mechanism.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include "mech_dev.hpp"
@@ -49,11 +57,12 @@ __device__ __forceinline__ void lds_add(double *p, double v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// A workgroup holds up to four wavefronts, each integrating its own cells in
+// A workgroup holds up to eight wavefronts, each integrating its own cells in
 // its own LDS region; they share one LDS copy of the species and reaction
-// records (placed first).  Within a cell only the wavefront synchronises: LDS
-// operations of one wavefront complete in order, so ordering them needs a
-// compiler barrier and a wavefront-scope fence, not a workgroup barrier.
+// records (placed first) and the pool of Jacobian slots.  Within a cell only
+// the wavefront synchronises: LDS operations of one wavefront complete in
+// order, so ordering them needs a compiler barrier and a wavefront-scope
+// fence, not a workgroup barrier.
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -65,6 +74,54 @@ extern __shared__ double lds_all[];
 __host__ __device__ inline int table_doubles(const MechDev &M) {
     return M.N * SPC_STRIDE + M.R * (int)(sizeof(RxnRec) / sizeof(double));
 }
+constexpr int kLockDoubles = 8;   // slot locks (up to 16 ints) ahead of the slots
+
+// The Jacobian slot of one wavefront.  With as many slots as wavefronts
+// (nslots == 0 here: a private slot) nothing is shared and the Jacobian stays
+// valid until the next assembly; otherwise a slot is taken from the pool with
+// an LDS compare-and-swap before assembly and given back once the iteration
+// matrix is in registers.  A holder never waits for anything, so every
+// waiting wavefront eventually gets a slot.
+struct JacSlot {
+    double *J;        // the held (or private) slot, row-major with stride ldj
+    double *pool;     // first slot of the pool
+    int *locks;       // one int per pooled slot: 0 free, 1 held
+    int nslots;       // pooled slots; 0: private slot
+    int held;         // index of the held pooled slot, -1 none
+    int jdoubles;
+
+    __device__ __forceinline__ bool pooled() const { return nslots > 0; }
+    __device__ __forceinline__ void acquire() {
+        if (!pooled() || held >= 0) return;
+        int s = -1;
+        while (true) {
+            if ((threadIdx.x & 63u) == 0) {
+                for (int k = 0; k < nslots; ++k) {
+                    int expect = 0;
+                    if (__hip_atomic_compare_exchange_strong(&locks[k], &expect, 1, __ATOMIC_ACQUIRE,
+                                                             __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_WORKGROUP)) {
+                        s = k;
+                        break;
+                    }
+                }
+            }
+            s = __builtin_amdgcn_readfirstlane(s);
+            if (s >= 0) break;
+            __builtin_amdgcn_s_sleep(2);
+        }
+        held = s;
+        J = pool + (size_t)s * jdoubles;
+        wave_sync();
+    }
+    __device__ __forceinline__ void release() {
+        if (!pooled() || held < 0) return;
+        wave_sync();
+        if ((threadIdx.x & 63u) == 0)
+            __hip_atomic_store(&locks[held], 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        held = -1;
+    }
+};
 
 // -----------------------------------------------------------------------------
 // f(y), and with JAC the analytic Jacobian into LDS (row-major, stride ldj).
@@ -72,7 +129,8 @@ __host__ __device__ inline int table_doubles(const MechDev &M) {
 // -----------------------------------------------------------------------------
 template <bool JAC, bool LT, bool FO>
 __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const double p,
-                                           const double y, double *__restrict__ lds) {
+                                           const double y, double *__restrict__ lds,
+                                           double *__restrict__ Jl) {
     // The memory clobber keeps the descriptor loads, and the opaque lane index
     // every per-lane address, local to this call instead of being hoisted out
     // of the step loop and held in registers across it.
@@ -81,7 +139,6 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
     asm volatile("" : "+v"(lane));
     const MechDev &M = *Mp;
     const int N = M.N, R = M.R, n = M.n, ldj = M.ldj;
-    double *__restrict__ Jl = lds + M.off_J;
     double *__restrict__ wl = lds + M.off_q;    // production rates omega_k (+ sentinel)
     double *__restrict__ Cl = lds + M.off_C;
     double *__restrict__ gl = lds + M.off_g;
@@ -441,7 +498,7 @@ __device__ __forceinline__ double lu_solve(const double (&a)[NP], int t, const d
 
 template <int NP>
 __device__ __forceinline__ void build_matrix(const MechDev *__restrict__ Mp,
-                                             const double *__restrict__ lds, double diag,
+                                             const double *__restrict__ J, double diag,
                                              double (&a)[NP]) {
     asm volatile("" ::: "memory");
     const MechDev &M = *Mp;
@@ -449,7 +506,7 @@ __device__ __forceinline__ void build_matrix(const MechDev *__restrict__ Mp,
     asm volatile("" : "+v"(lane));
     const int n = M.n;
     const bool row_ok = lane < n;
-    const double *Jl = lds + M.off_J + (row_ok ? lane : 0) * M.ldj;
+    const double *Jl = J + (row_ok ? lane : 0) * M.ldj;
 #pragma unroll
     for (int c = 0; c < NP; ++c) {
         const double x = Jl[c < n ? c : 0];
@@ -459,14 +516,16 @@ __device__ __forceinline__ void build_matrix(const MechDev *__restrict__ Mp,
     }
 }
 
-// One Rodas4 attempt of size h from y (f0 = f(y), J in LDS).  Returns false
+// One Rodas4 attempt of size h from y (f0 = f(y), J in the wavefront's slot,
+// which is given back once the iteration matrix is built).  Returns false
 // when M is singular.  ynew and err are per lane.
 template <int NP, bool LT, bool FO>
 __device__ __forceinline__ bool rodas_attempt(const MechDev *__restrict__ M, double p, double y,
-                                              double f0, double h, double *lds, double &ynew,
-                                              double &err) {
+                                              double f0, double h, double *lds, JacSlot &js,
+                                              double &ynew, double &err) {
     double a[NP];
-    build_matrix<NP>(M, lds, 1.0 / (kGamma * h), a);
+    build_matrix<NP>(M, js.J, 1.0 / (kGamma * h), a);
+    js.release();
     int t, pk;
     double dinv;
     const bool ok = lu_factor<NP>(a, t, dinv, pk);
@@ -482,7 +541,7 @@ __device__ __forceinline__ bool rodas_attempt(const MechDev *__restrict__ M, dou
             ys += kRodasA[s][2] * u2;
             ys += kRodasA[s][3] * u3;
             ys += kRodasA[s][4] * u4;
-            rv = rhs_eval<false, LT, FO>(M, p, ys, lds);
+            rv = rhs_eval<false, LT, FO>(M, p, ys, lds, nullptr);
             rv += (kRodasC[s][0] / h) * u0;
             rv += (kRodasC[s][1] / h) * u1;
             rv += (kRodasC[s][2] / h) * u2;
@@ -502,30 +561,45 @@ __device__ __forceinline__ bool rodas_attempt(const MechDev *__restrict__ M, dou
     return true;
 }
 
-// With LT, copies the species and reaction records into the shared LDS table
-// (whole workgroup, once per launch); returns this wavefront's region with its
-// sentinel entries set.
+// Per-wavefront LDS: the small region (returned) and the Jacobian slot.
+// Without LT (static launch: one wavefront per workgroup, records read from
+// global memory) the workgroup's LDS is [Jacobian][small region].  With LT
+// the whole workgroup first copies the species and reaction records into the
+// shared table (once per launch), and the LDS is [table][locks][jslots
+// Jacobian slots][one small region per wavefront]; jslots <= 0 or >= the
+// wavefronts of the workgroup gives every wavefront a private slot.
 template <bool LT>
-__device__ __forceinline__ double *init_lds(const MechDev *Mp) {
+__device__ __forceinline__ double *init_lds(const MechDev *Mp, int jslots, JacSlot &js) {
     const MechDev &M = *Mp;
+    const int jd = M.n * M.ldj;
+    js.jdoubles = jd;
+    js.held = -1;
+    double *lds;
     if (!LT) {
-        // one wavefront per workgroup, records read from global memory
-        double *lds = lds_all;
-        if (lane_id() == 0) {
-            lds[M.off_C + M.N] = 1.0;
-            lds[M.off_g + M.N] = 0.0;
-            lds[M.off_h + M.N] = 0.0;
-        }
-        wave_sync();
-        return lds;
+        js.J = lds_all;
+        js.pool = nullptr;
+        js.locks = nullptr;
+        js.nslots = 0;
+        lds = lds_all + jd;
+    } else {
+        const int wpb = (int)(blockDim.x >> 6), w = (int)(threadIdx.x >> 6);
+        const int ns = M.N * SPC_STRIDE, nr = M.R * (int)(sizeof(RxnRec) / sizeof(double));
+        const auto *spc = gbl(M.spc);
+        const double *rxd = reinterpret_cast<const double *>(M.rxn);
+        for (int i = threadIdx.x; i < ns; i += blockDim.x) lds_all[i] = spc[i];
+        for (int i = threadIdx.x; i < nr; i += blockDim.x) lds_all[ns + i] = gbl(rxd)[i];
+        int *locks = reinterpret_cast<int *>(lds_all + ns + nr);
+        const bool priv = jslots <= 0 || jslots >= wpb;
+        const int nslot = priv ? wpb : jslots;
+        if (threadIdx.x < 2 * kLockDoubles) locks[threadIdx.x] = 0;
+        double *pool = lds_all + ns + nr + kLockDoubles;
+        js.pool = pool;
+        js.locks = locks;
+        js.nslots = priv ? 0 : nslot;
+        js.J = priv ? pool + (size_t)w * jd : pool;
+        __syncthreads();
+        lds = pool + (size_t)nslot * jd + (size_t)w * M.lds_doubles;
     }
-    const int ns = M.N * SPC_STRIDE, nr = M.R * (int)(sizeof(RxnRec) / sizeof(double));
-    const auto *spc = gbl(M.spc);
-    const double *rxd = reinterpret_cast<const double *>(M.rxn);
-    for (int i = threadIdx.x; i < ns; i += blockDim.x) lds_all[i] = spc[i];
-    for (int i = threadIdx.x; i < nr; i += blockDim.x) lds_all[ns + i] = gbl(rxd)[i];
-    __syncthreads();
-    double *lds = lds_all + ns + nr + (threadIdx.x >> 6) * M.lds_doubles;
     if (lane_id() == 0) {
         lds[M.off_C + M.N] = 1.0;
         lds[M.off_g + M.N] = 0.0;
@@ -540,7 +614,7 @@ __device__ __forceinline__ double *init_lds(const MechDev *Mp) {
 // -----------------------------------------------------------------------------
 template <int NP, bool LT, bool FO>
 __device__ __forceinline__ void integrate_cell(const MechDev *__restrict__ M, const IntParams &P,
-                                               int64_t cell, double *lds) {
+                                               int64_t cell, double *lds, JacSlot &js) {
     const int lane = lane_id();
     const int n = M->n, N = M->N;
     const double dt = P.dt;
@@ -568,14 +642,24 @@ __device__ __forceinline__ void integrate_cell(const MechDev *__restrict__ M, co
     double hnext = h, t = 0.0;
     int nacc = 0, nrej = 0, status = 0;
     bool rej_last = false;
-    double f0 = rhs_eval<true, LT, FO>(M, p, y, lds);
+    // jac: the Jacobian of y is in the slot (a pooled slot is given back
+    // after each matrix build, so a rejected step assembles it again; the
+    // same y gives the same bits)
+    js.acquire();
+    double f0 = rhs_eval<true, LT, FO>(M, p, y, lds, js.J);
+    bool jac = true;
     while (t < dt) {
         if (nacc + nrej >= P.max_steps) { status = 1; break; }
         bool last = false;
         if (h >= dt - t) { h = dt - t; last = true; }
         if (h < P.hmin_frac * dt) { status = 2; break; }
+        if (!jac) {
+            js.acquire();
+            f0 = rhs_eval<true, LT, FO>(M, p, y, lds, js.J);
+        }
         double ynew = 0.0, ev = 0.0;
-        const bool ok = rodas_attempt<NP, LT, FO>(M, p, y, f0, h, lds, ynew, ev);
+        const bool ok = rodas_attempt<NP, LT, FO>(M, p, y, f0, h, lds, js, ynew, ev);
+        jac = !js.pooled();
         double e = 0.0;
         bool bad = !ok;
         if (ok) {
@@ -593,7 +677,11 @@ __device__ __forceinline__ void integrate_cell(const MechDev *__restrict__ M, co
             hnext = uniform_d(h * fac);
             h = hnext;
             rej_last = false;
-            if (t < dt) f0 = rhs_eval<true, LT, FO>(M, p, y, lds);
+            if (t < dt) {
+                js.acquire();
+                f0 = rhs_eval<true, LT, FO>(M, p, y, lds, js.J);
+                jac = true;
+            }
         } else {
             const double fac = bad ? 0.2 : fmax(0.2, 0.9 * pow(e, -0.25));
             h = uniform_d(h * fac);
@@ -601,6 +689,7 @@ __device__ __forceinline__ void integrate_cell(const MechDev *__restrict__ M, co
             rej_last = true;
         }
     }
+    js.release();
     if (status == 0 && wave_any(lane < n && !isfinite(y))) status = 3;
     if (lane == 0) P.T[cell] = y;
     else if (lane <= N) P.Y[(int64_t)(lane - 1) * P.ncells + cell] = y;
@@ -623,19 +712,27 @@ __device__ __forceinline__ void integrate_cell(const MechDev *__restrict__ M, co
 // saves).
 template <int NP, bool FO>
 __global__ __launch_bounds__(64) void k_integrate_plain(const MechDev *__restrict__ M, IntParams P) {
-    double *lds = init_lds<false>(M);
+    JacSlot js;
+    double *lds = init_lds<false>(M, 0, js);
     const int64_t cell = blockIdx.x;
     if (P.flags && P.flags[cell] >= 2) return;
-    integrate_cell<NP, false, FO>(M, P, cell, lds);
+    integrate_cell<NP, false, FO>(M, P, cell, lds, js);
 }
 
 // Persistent wavefronts draw cells from NSEG segments of the heavy-first queue
 // (segment x holds sorted positions x, x + NSEG, ...); wavefront w starts on
 // segment w % NSEG and steals from the next segments once its own is drained.
 // Every wavefront exits after NSEG consecutive empty segments.
+// Workgroups of up to eight wavefronts (four from 56 unknowns on, where
+// larger Jacobian slots leave room for fewer): with at most 256 registers per
+// lane, two wavefronts share each SIMD.
+__host__ __device__ constexpr int max_wpb(int NP) { return NP <= 54 ? 8 : 4; }
+
 template <int NP, bool FO>
-__global__ __launch_bounds__(256) void k_integrate_queue(const MechDev *__restrict__ M, IntParams P) {
-    double *lds = init_lds<true>(M);
+__global__ __launch_bounds__(64 * max_wpb(NP)) void k_integrate_queue(const MechDev *__restrict__ M,
+                                                                      IntParams P) {
+    JacSlot js;
+    double *lds = init_lds<true>(M, P.jslots, js);
     const int wpb = (int)(blockDim.x >> 6);
     const int wave = (int)blockIdx.x * wpb + (int)(threadIdx.x >> 6);
     // P.block_static: wavefront w owns cells [w B, (w + 1) B) and integrates
@@ -677,7 +774,7 @@ __global__ __launch_bounds__(256) void k_integrate_queue(const MechDev *__restri
             cell = P.queue[first + NSEG * q];
             ++q;
         }
-        integrate_cell<NP, true, FO>(M, P, cell, lds);
+        integrate_cell<NP, true, FO>(M, P, cell, lds, js);
     }
 }
 
@@ -685,32 +782,34 @@ __global__ __launch_bounds__(256) void k_integrate_queue(const MechDev *__restri
 template <int NP>
 __global__ __launch_bounds__(64) void k_eval_rhs_jac(const MechDev *__restrict__ M, IntParams P,
                                                      double *fout, double *Jout) {
-    double *lds = init_lds<true>(M);
+    JacSlot js;
+    double *lds = init_lds<true>(M, 0, js);
     const int64_t cell = blockIdx.x;
     const int lane = lane_id(), n = M->n, N = M->N;
     double y = 0.0;
     if (lane == 0) y = P.T[cell];
     else if (lane <= N) y = P.Y[(int64_t)(lane - 1) * P.ncells + cell];
-    const double f = rhs_eval<true, true, true>(M, P.p[cell], y, lds);
+    const double f = rhs_eval<true, true, true>(M, P.p[cell], y, lds, js.J);
     if (fout && lane < n) fout[cell * n + lane] = f;
     if (Jout)
         for (int i = lane; i < n * n; i += 64)
-            Jout[cell * n * n + i] = lds[M->off_J + (i / n) * M->ldj + (i % n)];
+            Jout[cell * n * n + i] = js.J[(i / n) * M->ldj + (i % n)];
 }
 
 template <int NP>
 __global__ __launch_bounds__(64) void k_rodas_step(const MechDev *__restrict__ M, IntParams P,
                                                    double h, double *ynew_out, double *err_out) {
-    double *lds = init_lds<true>(M);
+    JacSlot js;
+    double *lds = init_lds<true>(M, 0, js);
     const int64_t cell = blockIdx.x;
     const int lane = lane_id(), n = M->n, N = M->N;
     double y = 0.0;
     if (lane == 0) y = P.T[cell];
     else if (lane <= N) y = P.Y[(int64_t)(lane - 1) * P.ncells + cell];
     const double p = P.p[cell];
-    const double f0 = rhs_eval<true, true, true>(M, p, y, lds);
+    const double f0 = rhs_eval<true, true, true>(M, p, y, lds, js.J);
     double ynew = 0.0, err = 0.0;
-    const bool ok = rodas_attempt<NP, true, true>(M, p, y, f0, h, lds, ynew, err);
+    const bool ok = rodas_attempt<NP, true, true>(M, p, y, f0, h, lds, js, ynew, err);
     if (!ok) { ynew = NAN; err = NAN; }
     if (lane < n) {
         ynew_out[cell * n + lane] = ynew;
@@ -732,6 +831,7 @@ __global__ __launch_bounds__(64) void k_rodas_step(const MechDev *__restrict__ M
 #define CHEM_INTEGRATE_PART 0
 #endif
 
+int pick_np(int n);
 int wave_kernel_wpb(const MechDev &M);
 hipError_t launch_integrate_fo(int NP, const MechDev &M, const MechDev *Md, const IntParams &P,
                                int schedule, int grid, hipStream_t s);
@@ -744,17 +844,39 @@ int pick_np(int n) {
     return -1;
 }
 
-// Wavefronts per workgroup: as many as fit in one CU's LDS next to the shared
-// record table (4 for the 53-species mechanism: 28 KB of records + 4 x 28 KB).
-static constexpr size_t kLdsCap = 160 * 1024;
-int wave_kernel_wpb(const MechDev &M) {
-    for (int w : {4, 2, 1})
-        if (sizeof(double) * ((size_t)table_doubles(M) + (size_t)w * M.lds_doubles) <= kLdsCap) return w;
-    return 0;
-}
 #endif
-static size_t lds_bytes(const MechDev &M, int wpb) {
-    return sizeof(double) * ((size_t)table_doubles(M) + (size_t)wpb * M.lds_doubles);
+
+// Queue-kernel workgroup shape: the most wavefronts (up to max_wpb) whose
+// small regions fit in one CU's LDS next to the record table together with
+// Jacobian slots for at least half of them, and as many slots as then fit
+// (one per wavefront at most, which makes every slot private).  For the
+// 53-species mechanism: 8 wavefronts, 4 slots (27 KB of records, 8 x 4 KB,
+// 4 x 23 KB).
+static constexpr size_t kLdsCap = 160 * 1024;
+struct WaveLayout {
+    int wpb, jslots;
+};
+static WaveLayout wave_layout(const MechDev &M) {
+    const int np = pick_np(M.n);
+    if (np < 0) return {0, 0};
+    const size_t cap = kLdsCap / sizeof(double);
+    const size_t head = (size_t)table_doubles(M) + kLockDoubles, jd = (size_t)M.n * M.ldj;
+    for (int w = max_wpb(np); w >= 1; w /= 2) {
+        const size_t base = head + (size_t)w * M.lds_doubles;
+        if (base > cap) continue;
+        size_t js = (cap - base) / jd;
+        if (js < (size_t)(w + 1) / 2) continue;
+        if (js > (size_t)w) js = (size_t)w;
+        return {w, (int)js};
+    }
+    return {0, 0};
+}
+#if CHEM_INTEGRATE_PART == 0
+int wave_kernel_wpb(const MechDev &M) { return wave_layout(M).wpb; }
+#endif
+static size_t lds_bytes(const MechDev &M, const WaveLayout &L) {
+    return sizeof(double) * ((size_t)table_doubles(M) + kLockDoubles +
+                             (size_t)L.jslots * M.n * M.ldj + (size_t)L.wpb * M.lds_doubles);
 }
 
 // Host launchers: M is the host copy (sizes), Md the device copy the kernels read.
@@ -764,17 +886,20 @@ static size_t lds_bytes(const MechDev &M, int wpb) {
 template <int NP, bool FO>
 static hipError_t launch_integrate_np(const MechDev &M, const MechDev *Md, const IntParams &P,
                                       int schedule, int grid, hipStream_t s) {
-    const int wpb = wave_kernel_wpb(M);
-    const size_t sh = lds_bytes(M, wpb);
     if (schedule == 0) {
-        const size_t sh1 = sizeof(double) * (size_t)M.lds_doubles;
+        const size_t sh1 = sizeof(double) * ((size_t)M.n * M.ldj + (size_t)M.lds_doubles);
         hipFuncSetAttribute((const void *)k_integrate_plain<NP, FO>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh1);
         hipLaunchKernelGGL((k_integrate_plain<NP, FO>), dim3((unsigned)P.ncells), dim3(64), sh1, s, Md, P);
     } else {
+        const WaveLayout L = wave_layout(M);
+        if (L.wpb == 0 || L.jslots > 2 * kLockDoubles) return hipErrorInvalidConfiguration;
+        const size_t sh = lds_bytes(M, L);
+        IntParams Q = P;
+        Q.jslots = L.jslots;
         hipFuncSetAttribute((const void *)k_integrate_queue<NP, FO>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-        hipLaunchKernelGGL((k_integrate_queue<NP, FO>), dim3((unsigned)grid), dim3(64 * wpb), sh, s, Md, P);
+        hipLaunchKernelGGL((k_integrate_queue<NP, FO>), dim3((unsigned)grid), dim3(64 * L.wpb), sh, s, Md, Q);
     }
     return hipGetLastError();
 }
@@ -794,9 +919,10 @@ hipError_t launch_integrate(int NP, const MechDev &M, const MechDev *Md, const I
 // Workgroups of the queue kernel that fit on one CU.
 int queue_occupancy(int NP, const MechDev &M) {
     int blocks = 0;
-    const int wpb = wave_kernel_wpb(M);
-    if (wpb == 0) return 0;
-    const size_t sh = lds_bytes(M, wpb);
+    const WaveLayout L = wave_layout(M);
+    if (L.wpb == 0) return 0;
+    const size_t sh = lds_bytes(M, L);
+    const int wpb = L.wpb;
     switch (NP) {
 #define CASE(v)                                                                                 \
     case v:                                                                                     \
@@ -823,7 +949,7 @@ hipError_t launch_integrate_fo(int NP, const MechDev &M, const MechDev *Md, cons
 
 hipError_t launch_eval_rhs_jac(int NP, const MechDev &M, const MechDev *Md, const IntParams &P,
                                double *f, double *J, hipStream_t s) {
-    const size_t sh = lds_bytes(M, 1);
+    const size_t sh = lds_bytes(M, WaveLayout{1, 1});
     switch (NP) {
 #define CASE(v)                                                                                 \
     case v:                                                                                     \
@@ -839,7 +965,7 @@ hipError_t launch_eval_rhs_jac(int NP, const MechDev &M, const MechDev *Md, cons
 
 hipError_t launch_rodas_step(int NP, const MechDev &M, const MechDev *Md, const IntParams &P,
                              double h, double *ynew, double *err, hipStream_t s) {
-    const size_t sh = lds_bytes(M, 1);
+    const size_t sh = lds_bytes(M, WaveLayout{1, 1});
     switch (NP) {
 #define CASE(v)                                                                                 \
     case v:                                                                                     \

@@ -124,8 +124,9 @@ struct MechDev {
     const double *fo;       // [R][FO_STRIDE] fall-off parameters by reaction slot
     const double *plog;     // [R][PLOG_STRIDE] PLOG tables by reaction slot
     int has_fo;             // any fall-off or PLOG reaction
-    // LDS layout (offsets in doubles)
-    int off_J, off_q, off_C, off_g, off_h, off_e, off_cp, off_tb, off_sv, lds_doubles;
+    // per-wavefront LDS region (offsets in doubles); the Jacobian (n rows of
+    // stride ldj) has a slot of its own
+    int off_q, off_C, off_g, off_h, off_e, off_cp, off_tb, off_sv, lds_doubles;
 };
 
 struct IntParams {
@@ -148,6 +149,7 @@ struct IntParams {
     int block_static;       // persistent launch, contiguous block of cells per slot
     unsigned long long *stats;  // [8] device counters
     int *ref_status;        // nullable: receives the status of the reference cell (flag 1)
+    int jslots;             // Jacobian slots of a queue workgroup (set by the launcher)
 };
 
 }  // namespace chem
