@@ -28,6 +28,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "cells·dt/s (53-sp mech): plain vs balanced+surrogate at stated max err"
+# HBM bytes per integrated cell of one k_integrate_queue<54> launch, measured
+# by rocprofv3 counters on the current kernel (None: not measured for it)
+TRAFFIC_BYTES_PER_CELL = None
 
 
 def log(*a):
@@ -45,10 +48,13 @@ def make_state(field, torch):
                 ref=torch.zeros(1, dtype=torch.int64, device="cuda"))
 
 
-def run_mode(chem, mech, field, mode, steps, warmup, torch, synth, record_idx=None, gate=None):
+def run_mode(chem, mech, field, mode, steps, warmup, torch, synth, record_idx=None, gate=None,
+             after_warmup=None, snapshot=False):
     """Returns (ms_per_step, per-step stats of the timed steps, record, state).
     record: host copies of T, Y and flags of record_idx after the first step
-    (taken in the untimed warm-up)."""
+    (taken in the untimed warm-up).  after_warmup(S) runs between the warm-up
+    and the timed steps (launch tuning); with snapshot, S["snapshot"] holds a
+    copy of the state the timed steps start from."""
     from paper_2011_07978_amd.chem import CHEM_SCHED_PLAIN, CHEM_SCHED_QUEUE
     S = make_state(field, torch)
     Yf, Yo = synth.stream_fuel(mech), synth.stream_oxidiser(mech)
@@ -69,14 +75,21 @@ def run_mode(chem, mech, field, mode, steps, warmup, torch, synth, record_idx=No
                               stats=True)
 
     record = None
+    S["warmup_ms"] = []
     for w in range(warmup):
         st = one_step(S)
+        S["warmup_ms"].append(st["ms_total"])
         log(f"{mode} warmup {w + 1}/{warmup}: {st['ms_total']:.1f} ms, "
             f"steps {st['steps_accepted']}+{st['steps_rejected']}, surrogate {st['cells_surrogate']}")
         if w == 0 and record_idx is not None:
             ix = torch.as_tensor(record_idx, device="cuda")
             record = dict(T=S["T"][ix].cpu().numpy(), Y=S["Y"][:, ix].cpu().numpy(),
                           flags=S["flags"][ix].cpu().numpy())
+    torch.cuda.synchronize()
+    if after_warmup is not None:
+        after_warmup(S)
+    if snapshot:
+        S["snapshot"] = {k: v.clone() for k, v in S.items() if torch.is_tensor(v)}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = []
@@ -92,32 +105,42 @@ def run_mode(chem, mech, field, mode, steps, warmup, torch, synth, record_idx=No
     return ms, stats, record, S
 
 
-def graph_replay(chem, mech, field, steps, warmup, torch, synth):
-    """The balanced path's steps recorded once into a HIP graph (chem_graph_*)
-    and replayed: the same kernels without per-step host launches.  Returns
-    ms per step of one replay of `steps` recorded steps."""
+def graph_replay(chem, mech, field, mode, snapshot, steps, torch, synth, gate=None):
+    """The timed steps of `mode` recorded into one HIP graph (chem_graph_*) and
+    replayed once from the state they started from: the same kernels without
+    per-step host launches.  A context of its own on a created stream, with
+    the tuned launch shape and the surrogate's parameters; its workspaces are
+    warmed by one eager step on a scratch copy.  Returns ms per step."""
     from paper_2011_07978_amd.chem import CHEM_SCHED_QUEUE, Chem
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         g = Chem(0, stream=stream)
         g.set_mechanism(mech)
-        g.set_options(**{k: getattr(chem.options(), k) for k in ("queue_chunk", "slots_per_cu")},
-                      schedule=CHEM_SCHED_QUEUE)
+        o = chem.options()
+        g.set_options(schedule=CHEM_SCHED_QUEUE, queue_chunk=o.queue_chunk, slots_per_cu=o.slots_per_cu)
         g.reserve(field.n_cells)
-        S = make_state(field, torch)
+        if mode == "surrogate":
+            g.surrogate_set_params(chem.surrogate_get_params())
         Yf, Yo = synth.stream_fuel(mech), synth.stream_oxidiser(mech)
 
-        def step():
+        def step(S):
             g.map_reference(S["T"], S["p"], S["Y"], Yf, Yo, 1e-4, 1.0, False, flags=S["flags"],
                             ref_index=S["ref"])
-            g.integrate(S["T"], S["p"], S["Y"], field.dt, flags=S["flags"], ref_index=S["ref"],
-                        h=S["h"], cost=S["cost"], status=S["status"])
-        for _ in range(max(1, warmup)):
-            step()
+            if mode == "surrogate":
+                g.integrate_surrogate(S["T"], S["p"], S["Y"], field.dt, S["flags"], S["ref"], gate=gate,
+                                      h=S["h"], cost=S["cost"], status=S["status"])
+            else:
+                g.integrate(S["T"], S["p"], S["Y"], field.dt, flags=S["flags"], ref_index=S["ref"],
+                            h=S["h"], cost=S["cost"], status=S["status"])
+        scratch = {k: v.clone() for k, v in snapshot.items()}
+        step(scratch)                      # warm every workspace eagerly
+        stream.synchronize()
+        del scratch
+        G = {k: v.clone() for k, v in snapshot.items()}
         stream.synchronize()
         g.graph_begin()
         for _ in range(steps):
-            step()
+            step(G)
         graph = g.graph_end()
         stream.synchronize()
         t0 = time.perf_counter()
@@ -125,7 +148,8 @@ def graph_replay(chem, mech, field, steps, warmup, torch, synth):
         stream.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / steps
         graph.close()
-    log(f"graph replay of {steps} steps: {ms:.1f} ms per step")
+        del G
+    log(f"graph replay of {steps} {mode} steps: {ms:.1f} ms per step")
     return ms
 
 
@@ -238,16 +262,29 @@ def steady_state_error(chem, S, torch, surrogate_step, balanced_step):
                 max_abs_dY=float(dY.max()))
 
 
+def host_cores():
+    """CPU threads this process may use, capped at 16 (the CPU share of one
+    GPU on the benchmark hosts)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 def cpu_baseline(mech, field, synth, warmup, steps, budget_s=20.0, threads=None):
     """The oracle, as it stands, on uniformly drawn cells of the same field and
     the same path (mapping on the full field, integration of unmapped cells,
     step sizes carried from step to step).  It advances its own sample through
     the same warm-up steps (untimed; their cost bounds the sample size), then
-    times the same number of steps.  Cells are independent, so cells per second
-    on a uniform sample estimate the full field's rate."""
+    times the same number of steps three ways: all threads with
+    schedule(dynamic, 16) (the CPU analogue of a balanced run), all threads
+    with schedule(static) (unbalanced), and one thread on every threads-th
+    cell of the sample.  Cells are independent, so cells per second on a
+    uniform sample estimate the full field's rate."""
     from oracle import Oracle
     o = Oracle(mech)
-    threads = threads or min(16, os.cpu_count() or 1)
+    threads = threads or host_cores()
     Yf, Yo = synth.stream_fuel(mech), synth.stream_oxidiser(mech)
     flags_all, ref = o.map_reference(field.T, field.Y, Yf, Yo, 1e-4)
     order = np.random.default_rng(12345).permutation(field.n_cells)
@@ -267,19 +304,32 @@ def cpu_baseline(mech, field, synth, warmup, steps, budget_s=20.0, threads=None)
         spent += time.perf_counter() - t1
         Ts.append(T); Ys.append(Y); hs.append(h); idxs.append(idx)
     idx = np.concatenate(idxs)
-    T, Y, h = np.concatenate(Ts), np.concatenate(Ys, axis=1), np.concatenate(hs)
+    T0, Y0, h0 = np.concatenate(Ts), np.concatenate(Ys, axis=1), np.concatenate(hs)
     p = field.p[idx]
-    fl = flags_all[idx].copy()
-    t1 = time.perf_counter()
-    for _ in range(steps):
-        T, Y, h = o.integrate_batch(T, p, Y, field.dt, h=h, flags=fl, threads=threads,
-                                    schedule=1)[:3]
-    elapsed = time.perf_counter() - t1
-    return dict(value=idx.size * steps / elapsed, unit="cells·dt/s", cores=threads, kind="oracle",
+    fl0 = flags_all[idx].copy()
+
+    def timed(sel, nthreads, schedule):
+        T, Y, h = T0[sel], Y0[:, sel], h0[sel]
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            T, Y, h = o.integrate_batch(T, p[sel], Y, field.dt, h=h, flags=fl0[sel], threads=nthreads,
+                                        schedule=schedule)[:3]
+        el = time.perf_counter() - t1
+        return sel.size * steps / el, el
+
+    everything = np.arange(idx.size)
+    dyn, t_dyn = timed(everything, threads, 1)
+    sta, t_sta = timed(everything, threads, 0)
+    one_sel = everything[::threads]
+    one, t_one = timed(one_sel, 1, 0)
+    return dict(value=dyn, unit="cells·dt/s", cores=threads, kind="oracle",
                 sample=f"{idx.size} uniformly drawn cells of the {field.n_cells}-cell field; "
                        f"{warmup} untimed warm-up step(s) ({spent:.1f} s) then {steps} timed "
-                       f"step(s) ({elapsed:.1f} s), mapped cells skipped as on the GPU path, "
-                       f"{threads} OpenMP threads, schedule(dynamic,16)")
+                       f"step(s), mapped cells skipped as on the GPU path; value: {threads} OpenMP "
+                       f"threads, schedule(dynamic,16) ({t_dyn:.1f} s)",
+                static=dict(value=sta, cores=threads, schedule="static", seconds=t_sta),
+                one_core=dict(value=one, cores=1, cells=int(one_sel.size), seconds=t_one),
+                static_over_dynamic=sta / dyn)
 
 
 def main():
@@ -310,10 +360,13 @@ def main():
     ap.add_argument("--margin", type=float, default=0.01, help="gate: training-box margin")
     ap.add_argument("--max-dT", type=float, default=1.0, help="gate: largest predicted |dT| (K)")
     ap.add_argument("--T-max", type=float, default=1000.0, help="gate: hottest cell offered (K)")
-    ap.add_argument("--graph", action="store_true",
-                    help="also time the balanced steps recorded into one HIP graph")
-    ap.add_argument("--autotune", action="store_true",
-                    help="pick queue chunk and slots per CU on the first step's state first")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip replaying the timed steps from one recorded HIP graph")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip choosing queue chunk and slots per CU on the warmed-up state")
+    ap.add_argument("--surrogate-save", default="", help="write the trained surrogate parameters")
+    ap.add_argument("--surrogate-load", default="",
+                    help="load surrogate parameters instead of generating pairs and training")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -367,21 +420,36 @@ def main():
         f"{mech.n_reactions} reactions, dt {field.dt}")
     chem = Chem(0)
     chem.set_mechanism(mech)
-    threads = min(16, os.cpu_count() or 1)
+    threads = host_cores()
 
     sur = None
     gate = dict(tau_T=args.tau_T, y_min=-1e-10, margin=args.margin, max_dT=args.max_dT,
                 T_max=args.T_max)
     if use_sur:
-        sur = train_surrogate(chem, mech, args, torch, accounting)
+        if args.surrogate_load:
+            chem.surrogate_load(args.surrogate_load)
+            sur = dict(loaded=os.path.basename(args.surrogate_load))
+            log(f"surrogate parameters loaded from {args.surrogate_load}")
+        else:
+            sur = train_surrogate(chem, mech, args, torch, accounting)
+        if args.surrogate_save:
+            chem.surrogate_save(args.surrogate_save)
     chem.reserve(field.n_cells)
     tune = None
-    if args.autotune:
-        S0 = make_state(field, torch)
-        tune = chem.autotune(S0["T"], S0["p"], S0["Y"], field.dt)
-        o = chem.options()
-        log(f"autotune: {tune} -> schedule {o.schedule} chunk {o.queue_chunk} slots {o.slots_per_cu}")
-        del S0
+
+    def autotune(S):
+        """Launch shape of the queue from the warmed-up state (the timed steps'
+        own starting point): chem_autotune times every configuration on copies
+        of it; the fastest queue configuration is kept for every queue leg."""
+        nonlocal tune
+        res = chem.autotune(S["T"], S["p"], S["Y"], field.dt, flags=S["flags"], ref_index=S["ref"])
+        q = min((r for r in res if r[0] == 1), key=lambda r: r[3])
+        from paper_2011_07978_amd.chem import CHEM_SCHED_QUEUE
+        chem.set_options(schedule=CHEM_SCHED_QUEUE, queue_chunk=q[1], slots_per_cu=q[2])
+        tune = dict(chosen=dict(queue_chunk=q[1], slots_per_cu=q[2], ms=q[3]),
+                    measured=[dict(schedule="plain" if r[0] == 0 else "queue", queue_chunk=r[1],
+                                   slots_per_cu=r[2], ms=r[3]) for r in res])
+        log(f"autotune: {res} -> chunk {q[1]} slots {q[2]}")
 
     rec_idx = None
     if use_sur and not args.no_error and args.warmup >= 1:
@@ -389,8 +457,18 @@ def main():
 
     head_mode = "surrogate" if use_sur else "balanced"
     ms_h, st_h, rec, S_h = run_mode(chem, mech, field, head_mode, args.steps, args.warmup, torch,
-                                    synth, record_idx=rec_idx, gate=gate)
+                                    synth, record_idx=rec_idx, gate=gate,
+                                    after_warmup=None if args.no_autotune else autotune,
+                                    snapshot=not args.no_graph)
     value = field.n_cells / (ms_h / 1e3)
+    graph = None
+    if not args.no_graph:
+        ms_g = graph_replay(chem, mech, field, head_mode, S_h["snapshot"], args.steps, torch, synth,
+                            gate=gate)
+        graph = dict(ms_per_step=ms_g, value=field.n_cells / (ms_g / 1e3),
+                     note=f"the {args.steps} timed {head_mode} steps recorded into one HIP graph and "
+                          "replayed once from the same starting state, same launch shape")
+        del S_h["snapshot"]
     balanced = None
     if use_sur:
         ms_b, st_b, _, S_b = run_mode(chem, mech, field, "balanced", args.steps, args.warmup, torch,
@@ -409,11 +487,6 @@ def main():
                      integrate_ms=float(np.mean([s["ms_integrate"] for s in st_pl])))
         del S_p
 
-    graph = None
-    if args.graph:
-        ms_g = graph_replay(chem, mech, field, args.steps, args.warmup, torch, synth)
-        graph = dict(ms_per_step=ms_g, value=field.n_cells / (ms_g / 1e3),
-                     note="balanced path (no surrogate), steps recorded into one HIP graph")
 
     # roofline of the dominant kernel (the integration kernel), per launch
     sc = accounting.step_cost(mech)
@@ -422,12 +495,14 @@ def main():
     achieved = float(np.mean([f / (m * 1e-3) / 1e12 for f, m in zip(fl, kms)]))
     kname = "k_big_queue" if mech.n_species + 1 > 64 else "k_integrate_queue"
     # HBM bytes per integrated cell and launch of the wavefront kernel, from
-    # rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 1 GiB copy
-    # (profiles/k_integrate_queue_54__pmc_traffic_mapped_262k.md)
+    # the rocprofv3 FETCH_SIZE / WRITE_SIZE passes over this workload kept in
+    # profiles/ (scaled by the same counters over a copy kernel of known
+    # size); null when no pass of the current kernel exists
     traffic = None
     plain_kinetics = getattr(mech, "falloff", None) is None and getattr(mech, "plog_count", None) is None
-    if kname == "k_integrate_queue" and mech.n_species == 53 and plain_kinetics:
-        traffic = 8585.0 * float(np.mean([s["cells_integrated"] for s in st_h]))
+    if (kname == "k_integrate_queue" and mech.n_species == 53 and plain_kinetics
+            and TRAFFIC_BYTES_PER_CELL is not None):
+        traffic = TRAFFIC_BYTES_PER_CELL * float(np.mean([s["cells_integrated"] for s in st_h]))
     roof = dict(bound="alu", achieved=achieved, peak=accounting.FP64_VECTOR_PEAK_TFLOPS,
                 unit="TFLOP/s", frac=achieved / accounting.FP64_VECTOR_PEAK_TFLOPS, traffic=traffic,
                 traffic_unit="bytes per launch" if traffic else None,
@@ -464,14 +539,21 @@ def main():
             + (" + BF16 MLP surrogate with conservation and gate (tau_T %g K, max |dT| %g K, T <= %g K)"
                % (args.tau_T, args.max_dT, args.T_max)
                if use_sur else "")
-            + " + heavy-first queue + Rodas4 + mapped update")
+            + " + heavy-first queue + Rodas4 + mapped update"
+            + f"; timed: flow steps {args.warmup + 1}-{args.warmup + args.steps} of a run from the "
+              f"pristine field, after {args.warmup} untimed warm-up step(s)")
     out = {
         "metric": METRIC, "value": value, "unit": "cells·dt/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_h,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": desc, "cells": field.n_cells, "species": mech.n_species,
-                   "reactions": mech.n_reactions, "dt": field.dt, "parallelism": "single GPU"},
+                   "reactions": mech.n_reactions, "dt": field.dt, "parallelism": "single GPU",
+                   "timed_window": [args.warmup + 1, args.warmup + args.steps]},
+        "step_ms": [s["ms_total"] for s in st_h],
+        "integrate_kernel_ms": kms,
+        "first_step_ms": S_h["warmup_ms"][0] if S_h["warmup_ms"] else None,
+        "warmup_ms": S_h["warmup_ms"],
         "plain": plain,
         "balanced_without_surrogate": balanced,
         "speedup_vs_plain": (value / plain["value"]) if plain else None,
