@@ -364,10 +364,15 @@ def main():
                     help="skip replaying the timed steps from one recorded HIP graph")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip choosing queue chunk and slots per CU on the warmed-up state")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time the headline path alone (no comparison legs, oracle error or CPU "
+                         "baseline; for profiler runs)")
     ap.add_argument("--surrogate-save", default="", help="write the trained surrogate parameters")
     ap.add_argument("--surrogate-load", default="",
                     help="load surrogate parameters instead of generating pairs and training")
     args = ap.parse_args()
+    if args.headline_only:
+        args.no_plain = args.no_cpu = args.no_error = args.no_graph = args.no_autotune = True
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures the path on one GPU only (asked for --gpus {args.gpus}, "
@@ -470,7 +475,7 @@ def main():
                           "replayed once from the same starting state, same launch shape")
         del S_h["snapshot"]
     balanced = None
-    if use_sur:
+    if use_sur and not args.headline_only:
         ms_b, st_b, _, S_b = run_mode(chem, mech, field, "balanced", args.steps, args.warmup, torch,
                                       synth)
         balanced = dict(value=field.n_cells / (ms_b / 1e3), ms_per_step=ms_b,
@@ -553,6 +558,7 @@ def main():
         "step_ms": [s["ms_total"] for s in st_h],
         "integrate_kernel_ms": kms,
         "first_step_ms": S_h["warmup_ms"][0] if S_h["warmup_ms"] else None,
+        "max_cell_steps": [s["max_cell_steps"] for s in st_h],
         "warmup_ms": S_h["warmup_ms"],
         "plain": plain,
         "balanced_without_surrogate": balanced,
