@@ -28,9 +28,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "cells·dt/s (53-sp mech): plain vs balanced+surrogate at stated max err"
-# HBM bytes per integrated cell of one k_integrate_queue<54> launch, measured
-# by rocprofv3 counters on the current kernel (None: not measured for it)
-TRAFFIC_BYTES_PER_CELL = None
+# HBM bytes per attempted Rodas4 step of k_integrate_queue<54> (FETCH_SIZE x 2
+# + WRITE_SIZE, the factors from a 1 GiB copy), from the counter passes over
+# the headline workload in profiles/k_integrate_queue_54__counters_surrogate_field_1M.md
+# (None: not measured for the current kernel).  Nearly all of it is register
+# spill traffic, proportional to attempted steps.
+TRAFFIC_BYTES_PER_ATTEMPT = 5279.4
 
 
 def log(*a):
@@ -499,15 +502,15 @@ def main():
     kms = [s["ms_integrate"] for s in st_h]
     achieved = float(np.mean([f / (m * 1e-3) / 1e12 for f, m in zip(fl, kms)]))
     kname = "k_big_queue" if mech.n_species + 1 > 64 else "k_integrate_queue"
-    # HBM bytes per integrated cell and launch of the wavefront kernel, from
-    # the rocprofv3 FETCH_SIZE / WRITE_SIZE passes over this workload kept in
-    # profiles/ (scaled by the same counters over a copy kernel of known
-    # size); null when no pass of the current kernel exists
+    # HBM bytes per launch of the wavefront kernel, from the rocprofv3
+    # FETCH_SIZE / WRITE_SIZE passes over the headline workload (scaled by the
+    # same counters over a copy kernel of known size), per attempted step
     traffic = None
     plain_kinetics = getattr(mech, "falloff", None) is None and getattr(mech, "plog_count", None) is None
     if (kname == "k_integrate_queue" and mech.n_species == 53 and plain_kinetics
-            and TRAFFIC_BYTES_PER_CELL is not None):
-        traffic = TRAFFIC_BYTES_PER_CELL * float(np.mean([s["cells_integrated"] for s in st_h]))
+            and TRAFFIC_BYTES_PER_ATTEMPT is not None):
+        traffic = TRAFFIC_BYTES_PER_ATTEMPT * float(np.mean([s["steps_accepted"] + s["steps_rejected"]
+                                                             for s in st_h]))
     roof = dict(bound="alu", achieved=achieved, peak=accounting.FP64_VECTOR_PEAK_TFLOPS,
                 unit="TFLOP/s", frac=achieved / accounting.FP64_VECTOR_PEAK_TFLOPS, traffic=traffic,
                 traffic_unit="bytes per launch" if traffic else None,
