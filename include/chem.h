@@ -396,15 +396,24 @@ typedef struct {
 /* Time launch configurations on copies of a sample state and keep the fastest
  * in the context's options: the plain launch, and the work queue with
  * queue_chunk in {1, 2, 4, 8} and slots_per_cu in {occupancy / 2, occupancy}
- * (occupancy = workgroups of the integration kernel that fit on one CU).  One
- * untimed pass first records the per-cell cost that orders the queue.
+ * (occupancy = workgroups of the integration kernel that fit on one CU; one
+ * slot choice when they are equal).  One untimed pass first records the
+ * per-cell cost that orders the queue.
  * T, p, Y, flags, ref_index as for chem_integrate (device, read only).
  * results (host, nullable) receives up to max_results entries in the order
  * above, *n_results (nullable) their count.  Synchronous; allocates scratch
- * for one copy of the state. */
+ * for one copy of the state.
+ * The timings are kept for the life of the process, keyed by the device's
+ * architecture, the mechanism's species and reaction counts, the integration
+ * kernel (wavefront or workgroup, with or without fall-off/PLOG code),
+ * whether flags is given, and n_cells rounded down to a power of two.  A later
+ * call with the same key, from any context, reports the kept timings and sets
+ * the options from them without launching anything. */
 int chem_autotune(chem_ctx *ctx, int64_t n_cells, const double *T, const double *p, const double *Y,
                   double dt, const uint8_t *flags, const int64_t *ref_index,
                   chem_tune_entry *results, int32_t max_results, int32_t *n_results);
+/* Drop every kept autotune timing, so that the next chem_autotune measures. */
+void chem_autotune_forget(void);
 
 /* Evaluate f(y) and the analytic Jacobian for n cells (kernel-level check of
  * the rate and Jacobian code of the integrator).  T, p [n], Y [N*n] device;

@@ -109,9 +109,10 @@ EXPORTS = ["chem_create", "chem_destroy", "chem_set_stream", "chem_last_error",
            "chem_surrogate_save", "chem_surrogate_load", "chem_surrogate_forward",
            "chem_surrogate_forward_fused",
            "chem_surrogate_loss_grad", "chem_graph_begin", "chem_graph_end", "chem_graph_launch",
-           "chem_graph_destroy", "chem_autotune"]
+           "chem_graph_destroy", "chem_autotune", "chem_autotune_forget"]
 _VOID = ("chem_destroy", "chem_default_options", "chem_last_error", "chem_default_train_params",
-         "chem_default_gate_params", "chem_surrogate_param_count", "chem_graph_destroy")
+         "chem_default_gate_params", "chem_surrogate_param_count", "chem_graph_destroy",
+         "chem_autotune_forget")
 
 _lib = None
 
@@ -174,6 +175,8 @@ def load_library(path: str = LIB_PATH):
     L.chem_graph_destroy.restype = None
     L.chem_autotune.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_double, vp, vp,
                                 C.POINTER(TuneEntry), C.c_int32, C.POINTER(C.c_int32)]
+    L.chem_autotune_forget.argtypes = []
+    L.chem_autotune_forget.restype = None
     for name in EXPORTS:
         if name not in _VOID:
             getattr(L, name).restype = C.c_int
@@ -440,9 +443,13 @@ class Chem:
         self._check(self.L.chem_graph_end(self.h, C.byref(g)), "chem_graph_end")
         return Graph(self, g)
 
-    def autotune(self, T, p, Y, dt, flags=None, ref_index=None):
+    def autotune(self, T, p, Y, dt, flags=None, ref_index=None, remeasure=False):
         """chem_autotune; returns [(schedule, queue_chunk, slots_per_cu, ms)] and
-        leaves the fastest configuration in the context's options."""
+        leaves the fastest configuration in the context's options.  Timings
+        kept from an earlier call with the same key are reused unless
+        remeasure (chem_autotune_forget first)."""
+        if remeasure:
+            self.L.chem_autotune_forget()
         res = (TuneEntry * 16)()
         cnt = C.c_int32(0)
         self._check(self.L.chem_autotune(self.h, T.shape[0], _ptr(T), _ptr(p), _ptr(Y), float(dt),

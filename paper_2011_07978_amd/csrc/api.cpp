@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -1310,6 +1311,29 @@ void chem_graph_destroy(chem_graph *g) {
 }
 
 // ---------------------------------------------------------- autotune -------
+// chem_autotune's measurements, kept for the process and keyed by device
+// architecture, mechanism size (species, reactions), integrator (wavefront or
+// workgroup kernel, with or without fall-off / PLOG code), whether mapping
+// flags take part, and the sample's size rounded down to a power of two.
+static std::mutex g_tune_mu;
+static std::map<std::string, std::vector<chem_tune_entry>> g_tune_cache;
+
+static std::string tune_key(const chem_ctx *c, int64_t n, bool mapped) {
+    hipDeviceProp_t prop;
+    std::string arch = hipGetDeviceProperties(&prop, c->device) == hipSuccess ? prop.gcnArchName : "?";
+    int lg = 0;
+    while ((int64_t)2 << lg <= n) ++lg;
+    char buf[160];
+    snprintf(buf, sizeof buf, "%s/N%d/R%d/%s%s/%s/2^%d", arch.c_str(), c->N, c->R, c->big ? "wg" : "wave",
+             c->M.has_fo ? "+fo" : "", mapped ? "mapped" : "plain", lg);
+    return buf;
+}
+
+void chem_autotune_forget(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache.clear();
+}
+
 int chem_autotune(chem_ctx *c, int64_t n, const double *T, const double *p, const double *Y,
                   double dt, const uint8_t *flags, const int64_t *ref_index, chem_tune_entry *res,
                   int32_t max_res, int32_t *n_res) {
@@ -1321,6 +1345,24 @@ int chem_autotune(chem_ctx *c, int64_t n, const double *T, const double *p, cons
     if (rc) return rc;
     if (capturing(c)) return fail(c, CHEM_E_CAPTURE_UNSAFE, "autotune during capture");
     HIPCHK(c, hipSetDevice(c->device));
+    const std::string key = tune_key(c, n, flags != nullptr);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            const std::vector<chem_tune_entry> &v = it->second;
+            size_t b = 0;
+            for (size_t i = 0; i < v.size(); ++i) {
+                if (v[i].ms < v[b].ms) b = i;
+                if ((int32_t)i < max_res) res[i] = v[i];
+            }
+            c->opt.schedule = v[b].schedule;
+            c->opt.queue_chunk = v[b].queue_chunk;
+            c->opt.slots_per_cu = v[b].slots_per_cu;
+            if (n_res) *n_res = std::min((int32_t)v.size(), max_res);
+            return CHEM_OK;
+        }
+    }
     if ((rc = chem_reserve(c, n))) return rc;
     const size_t nY = (size_t)c->N * n;
     double *dT = nullptr, *dY = nullptr, *dh = nullptr;
@@ -1362,10 +1404,13 @@ int chem_autotune(chem_ctx *c, int64_t n, const double *T, const double *p, cons
     std::vector<Cand> cands;
     const int occ = std::max(1, c->occ);
     cands.push_back({CHEM_SCHED_PLAIN, 0, 0});
-    for (int slots : {std::max(1, occ / 2), occ})
+    std::vector<int> slot_choices{std::max(1, occ / 2)};
+    if (occ != slot_choices[0]) slot_choices.push_back(occ);   // occ == 1 leaves one choice
+    for (int slots : slot_choices)
         for (int chunk : {1, 2, 4, 8}) cands.push_back({CHEM_SCHED_QUEUE, chunk, slots});
     double best = INFINITY;
     chem_options best_opt = saved;
+    std::vector<chem_tune_entry> measured;
     int k = 0;
     for (const Cand &cd : cands) {
         c->opt = saved;
@@ -1381,11 +1426,16 @@ int chem_autotune(chem_ctx *c, int64_t n, const double *T, const double *p, cons
                         ctx_work(c));
         if (rc < 0) { c->opt = saved; release(); return rc; }
         if (k < max_res) res[k] = chem_tune_entry{cd.sched, cd.chunk, cd.slots, st.ms_total};
+        measured.push_back(chem_tune_entry{cd.sched, cd.chunk, cd.slots, st.ms_total});
         ++k;
         if (st.ms_total < best) { best = st.ms_total; best_opt = c->opt; }
     }
     c->opt = best_opt;
     if (n_res) *n_res = std::min(k, max_res);
     release();
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = measured;
+    }
     return CHEM_OK;
 }

@@ -71,8 +71,16 @@ __device__ __forceinline__ void wave_sync() {
 
 extern __shared__ double lds_all[];
 
+// The workgroup's LDS copy of the records is field-major: field f of species
+// k at f N + k, field f of reaction j at N SPC_STRIDE + f R + j (a reaction
+// record is 8 doubles, its four index words packed two per double), so the
+// lanes of a wavefront, each on its own species or reaction, read
+// consecutive doubles.
+constexpr int RXN_FIELDS = (int)(sizeof(RxnRec) / sizeof(double));
+static_assert(RXN_FIELDS == 8, "reaction record of 8 doubles");
+
 __host__ __device__ inline int table_doubles(const MechDev &M) {
-    return M.N * SPC_STRIDE + M.R * (int)(sizeof(RxnRec) / sizeof(double));
+    return M.N * SPC_STRIDE + M.R * RXN_FIELDS;
 }
 constexpr int kLockDoubles = 8;   // slot locks (up to 16 ints) ahead of the slots
 
@@ -156,17 +164,19 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
     // species thermo (NASA-7 single range), Horner form
     double cpR = 0.0, hRT = 0.0, gRT = 0.0, dcpR = 0.0, invWk = 0.0, Wk = 0.0;
     if (sp) {
-        const double *a = LT ? lds_all + k * SPC_STRIDE : (const double *)(gbl(M.spc) + k * SPC_STRIDE);
-        const double a1 = a[0], a2 = a[1], a3 = a[2], a4 = a[3], a5 = a[4], a6 = a[5], a7 = a[6];
-        const double h2 = a[7], h3 = a[8], h4 = a[9], h5 = a[10];
-        const double s3 = a[11], s4 = a[12], s5 = a[13];
+        const double *a = LT ? lds_all + k : (const double *)(gbl(M.spc) + k * SPC_STRIDE);
+        const int fs = LT ? N : 1;   // distance between fields
+        const double a1 = a[0], a2 = a[fs], a3 = a[2 * fs], a4 = a[3 * fs], a5 = a[4 * fs];
+        const double a6 = a[5 * fs], a7 = a[6 * fs];
+        const double h2 = a[7 * fs], h3 = a[8 * fs], h4 = a[9 * fs], h5 = a[10 * fs];
+        const double s3 = a[11 * fs], s4 = a[12 * fs], s5 = a[13 * fs];
         cpR = a1 + T * (a2 + T * (a3 + T * (a4 + T * a5)));
         hRT = a1 + T * (h2 + T * (h3 + T * (h4 + T * h5))) + a6 * invT;
         const double sR = a1 * lnT + T * (a2 + T * (s3 + T * (s4 + T * s5))) + a7;
         gRT = hRT - sR;
         if (JAC) dcpR = a2 + T * (2.0 * a3 + T * (3.0 * a4 + T * (4.0 * a5)));
-        Wk = a[14];
-        invWk = a[15];
+        Wk = a[14 * fs];
+        invWk = a[15 * fs];
     }
     const double yw = sp ? y * invWk : 0.0;
     const double sumYW = wave_sum(yw);
@@ -193,10 +203,26 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
     // the sentinel entry N)
     const double ln_patm_RT = log(P_ATM / (RU_ERG * T));
     const double lnp = FO ? log(p) : 0.0;
-    const RxnRec *rxn = LT ? reinterpret_cast<const RxnRec *>(lds_all + N * SPC_STRIDE)
-                           : (const RxnRec *)gbl(M.rxn);
+    const double *rtab = lds_all + N * SPC_STRIDE;
+    const RxnRec *rxn = (const RxnRec *)gbl(M.rxn);
     auto reaction = [&](const int j, const bool valid) {
-        const auto &rec = rxn[j];
+        RxnRec rec;
+        if (LT) {
+            const double *r = rtab + j;
+            rec.lnA = r[0];
+            rec.b = r[R];
+            rec.EaR = r[2 * R];
+            rec.eff[0] = r[3 * R];
+            rec.eff[1] = r[4 * R];
+            rec.eff[2] = r[5 * R];
+            const double w01 = r[6 * R], w23 = r[7 * R];
+            rec.idx[0] = __double2loint(w01);
+            rec.idx[1] = __double2hiint(w01);
+            rec.idx[2] = __double2loint(w23);
+            rec.idx[3] = __double2hiint(w23);
+        } else {
+            rec = rxn[j];
+        }
         const int ix0 = rec.idx[0], ix1 = rec.idx[1], ix2 = rec.idx[2], ix3 = rec.idx[3];
         const int r0 = ix0 & 0xffff, r1 = (int)((unsigned)ix0 >> 16);
         const int p0 = ix1 & 0xffff, p1 = (int)((unsigned)ix1 >> 16);
@@ -309,7 +335,7 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
                 // 1/W_i from the species records in the shared table (broadcast reads)
 #pragma unroll 8
                 for (int i = 0; i < N; ++i)
-                    row[1 + i] = lds_all[i * SPC_STRIDE + 15] * (Wk * (row[1 + i] + tbk) + cst);
+                    row[1 + i] = lds_all[15 * N + i] * (Wk * (row[1 + i] + tbk) + cst);
             } else {
                 const auto *iw = gbl(M.invW);
 #pragma unroll 8
@@ -583,11 +609,15 @@ __device__ __forceinline__ double *init_lds(const MechDev *Mp, int jslots, JacSl
         lds = lds_all + jd;
     } else {
         const int wpb = (int)(blockDim.x >> 6), w = (int)(threadIdx.x >> 6);
-        const int ns = M.N * SPC_STRIDE, nr = M.R * (int)(sizeof(RxnRec) / sizeof(double));
+        const int ns = M.N * SPC_STRIDE, nr = M.R * RXN_FIELDS;
         const auto *spc = gbl(M.spc);
         const double *rxd = reinterpret_cast<const double *>(M.rxn);
-        for (int i = threadIdx.x; i < ns; i += blockDim.x) lds_all[i] = spc[i];
-        for (int i = threadIdx.x; i < nr; i += blockDim.x) lds_all[ns + i] = gbl(rxd)[i];
+        for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+            const int k = i / SPC_STRIDE, f = i - k * SPC_STRIDE;
+            lds_all[f * M.N + k] = spc[i];
+        }
+        for (int i = threadIdx.x; i < nr; i += blockDim.x)
+            lds_all[ns + (i & (RXN_FIELDS - 1)) * M.R + (i / RXN_FIELDS)] = gbl(rxd)[i];
         int *locks = reinterpret_cast<int *>(lds_all + ns + nr);
         const bool priv = jslots <= 0 || jslots >= wpb;
         const int nslot = priv ? wpb : jslots;

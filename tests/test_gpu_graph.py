@@ -114,13 +114,27 @@ def test_autotune_keeps_fastest_and_never_changes_results():
     c = chem_for(mech)
     T, p, Y = dev(f.T), dev(f.p), dev(f.Y)
     T0, Y0 = host(T).copy(), host(Y).copy()
-    res = c.autotune(T, p, Y, f.dt)
+    res = c.autotune(T, p, Y, f.dt, remeasure=True)
     print(res)
-    assert len(res) == 9
+    # the plain launch, then queue_chunk 1, 2, 4, 8 for each distinct slots_per_cu
+    # (one when a single workgroup of the integration kernel fills a CU)
+    slots = sorted({r[2] for r in res[1:]})
+    assert res[0][:3] == (0, 0, 0) and 1 <= len(slots) <= 2
+    assert [r[:3] for r in res[1:]] == [(1, k, s) for s in slots for k in (1, 2, 4, 8)]
     assert np.array_equal(host(T), T0) and np.array_equal(host(Y), Y0)   # input untouched
     best = min(res, key=lambda r: r[3])
     o = c.options()
     assert (o.schedule, o.queue_chunk, o.slots_per_cu) == best[:3]
+    # kept for the process: a second context with the same mechanism and sample
+    # size gets the same timings and choice back without measuring
+    say("autotune kept timings, second context")
+    c2 = chem_for(mech)
+    assert c2.autotune(T, p, Y, f.dt) == res
+    o2 = c2.options()
+    assert (o2.schedule, o2.queue_chunk, o2.slots_per_cu) == best[:3]
+    say("autotune remeasure")
+    again = c2.autotune(T, p, Y, f.dt, remeasure=True)
+    assert [r[:3] for r in again] == [r[:3] for r in res]
     tuned = run_integrate(c, f)
     c.set_options(schedule=CHEM_SCHED_QUEUE, queue_chunk=0, slots_per_cu=0)
     default = run_integrate(c, f)
