@@ -723,7 +723,8 @@ int chem_set_mechanism(chem_ctx *c, const chem_mech_desc *m) {
     int off = 0;
     M.off_q = off; off += N + 1;   // production rates (+ sentinel)
     M.off_C = off; off += N + 1;
-    M.off_g = off; off += N + 1;
+    M.off_g = off; off += N + 1;    // exp(g_k) RT/p_atm (+ sentinel 1)
+    M.off_gi = off; off += N + 1;   // its reciprocal (+ sentinel 1)
     M.off_h = off; off += N + 1;
     M.off_e = off; off += N;
     M.off_cp = off; off += N;

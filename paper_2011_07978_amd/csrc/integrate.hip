@@ -150,6 +150,7 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
     double *__restrict__ wl = lds + M.off_q;    // production rates omega_k (+ sentinel)
     double *__restrict__ Cl = lds + M.off_C;
     double *__restrict__ gl = lds + M.off_g;
+    double *__restrict__ gil = lds + M.off_gi;
     double *__restrict__ hl = lds + M.off_h;
     double *__restrict__ el = lds + M.off_e;
     double *__restrict__ cpl = lds + M.off_cp;
@@ -157,6 +158,7 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
 
     const double T = readlane_d(y, 0);
     const double lnT = log(T);
+    const double ln_patm_RT = kLnPatmRu - lnT;   // ln(p_atm / (R T))
     const double invT = 1.0 / T;
     const bool sp = lane >= 1 && lane <= N;
     const int k = sp ? lane - 1 : 0;
@@ -184,7 +186,11 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
     const double Ctot = rho * sumYW;
     if (sp) {
         Cl[k] = rho * yw;
-        gl[k] = gRT;
+        // species factors of the equilibrium constant: a reaction's
+        // 1 / K_c = prod_products E_k / prod_reactants E_k, E_k = exp(g_k) RT / p_atm
+        const double gx = gRT - ln_patm_RT;
+        gl[k] = exp(gx);
+        gil[k] = exp(-gx);
         if (JAC) {
             hl[k] = hRT;
             el[k] = hRT * invWk;
@@ -201,7 +207,6 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
     // reaction pass: rates of progress scattered to the production rates of
     // their reactant and product slots (LDS float atomics; missing slots hit
     // the sentinel entry N)
-    const double ln_patm_RT = log(P_ATM / (RU_ERG * T));
     const double lnp = FO ? log(p) : 0.0;
     const double *rtab = lds_all + N * SPC_STRIDE;
     const RxnRec *rxn = (const RxnRec *)gbl(M.rxn);
@@ -232,13 +237,11 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
         const int es0 = (ix3 >> 8) & 0xff, es1 = (ix3 >> 16) & 0xff;
         const int es2 = (int)((unsigned)ix3 >> 24);
         const double Cr0 = Cl[r0], Cr1 = Cl[r1], Cp0 = Cl[p0], Cp1 = Cl[p1], Cp2 = Cl[p2];
-        const double dG = -gl[r0] - gl[r1] + gl[p0] + gl[p1] + gl[p2];
         double lnAj = rec.lnA, bj = rec.b, EaRj = rec.EaR;
         if (FO && (tbw & TB_PLOG)) plog_arrhenius(M.plog + (size_t)j * PLOG_STRIDE, lnp, lnAj, bj, EaRj);
         const double ln_kf = lnAj + bj * lnT - EaRj * invT;
-        const double ln_Kc = -dG + snu * ln_patm_RT;
         const double kf = exp(ln_kf);
-        const double kr = exp(ln_kf - ln_Kc);
+        const double kr = kf * ((gl[p0] * gil[r0]) * (gl[p1] * gil[r1]) * gl[p2]);
         const double Pf = Cr0 * Cr1;
         const double Pr = Cp0 * Cp1 * Cp2;
         const double e0v = rec.eff[0], e1v = rec.eff[1], e2v = rec.eff[2];
@@ -411,15 +414,18 @@ struct PivotSearch {
 constexpr int kSearchStages = 10;
 constexpr int kColsPerStage = 4;
 
-// LU with partial pivoting, row-per-lane.  On return lane r holds its row of
-// L (columns before its pivot step t) and U (columns from t on); dinv = 1/U_tt;
-// lane k holds pk = the lane that became pivot at step k.
+// LU with partial pivoting, row-per-lane.  No row moves while factorising:
+// a lane remembers the step t at which its row became pivot.  At the end the
+// rows are put in pivot order (one ds_bpermute per register), so on return
+// lane k holds the row that was pivot at step k: L in columns before k, U from
+// k on; dinv = 1/U_kk; pk = the lane that row came from (identity beyond the
+// matrix).
 template <int NP>
-__device__ __forceinline__ bool lu_factor(double (&a)[NP], int &t, double &dinv, int &pk) {
+__device__ __forceinline__ bool lu_factor(double (&a)[NP], double &dinv, int &pk) {
     int lane = lane_id();
     asm volatile("" : "+v"(lane));
     const bool active = lane < NP;
-    t = -1;
+    int t = -1;
     dinv = 0.0;
     PivotSearch ps;
 #pragma unroll
@@ -460,22 +466,24 @@ __device__ __forceinline__ bool lu_factor(double (&a)[NP], int &t, double &dinv,
     const bool bad = active && (t < 0 || !(fabs(dinv) < INFINITY));
     const int dst = active && t >= 0 ? t : lane;
     pk = __builtin_amdgcn_ds_permute(dst << 2, lane);
+#pragma unroll
+    for (int j = 0; j < NP; ++j) a[j] = shfl_d(a[j], pk);
+    dinv = shfl_d(dinv, pk);
     return !wave_any(bad);
 }
 
-// Solve with the factors of lu_factor.  Pivot step k's value is read from
-// lane pk[k] before that lane's own update at step k, so every lane updates
-// unconditionally: lanes whose value was already taken only accumulate terms
-// nobody reads.  The values taken (y_k forward, x_k backward) are kept in LDS
-// (sv, 2 x 64 doubles of this wavefront), written by lane 0 eight at a time;
-// lane k returns x_k.
+// Solve with the factors of lu_factor (rows in pivot order).  b is first put
+// in the same order; step k's value is read from lane k before that lane's
+// own update at step k, so every lane updates unconditionally: lanes whose
+// value was already taken only accumulate terms nobody reads.  The values
+// taken (y_k forward, x_k backward) are kept in LDS (sv, 2 x 64 doubles of
+// this wavefront), written by lane 0 eight at a time; lane k returns x_k.
 template <int NP>
-__device__ __forceinline__ double lu_solve(const double (&a)[NP], int t, const double dinv,
-                                           int pk, double b, double *sv) {
-    // keep the pivot lookups inside this call (not hoisted across calls, where
-    // they would hold ~NP scalar registers)
-    asm volatile("" : "+v"(pk), "+v"(t));
+__device__ __forceinline__ double lu_solve(const double (&a)[NP], const double dinv, int pk,
+                                           double b, double *sv) {
+    asm volatile("" : "+v"(pk));
     const int lane = lane_id();
+    b = shfl_d(b, pk);
 #pragma unroll
     for (int k0 = 0; k0 < NP; k0 += 8) {
         double yv[8];
@@ -483,8 +491,7 @@ __device__ __forceinline__ double lu_solve(const double (&a)[NP], int t, const d
         for (int u = 0; u < 8; ++u) {
             const int k = k0 + u;
             if (k < NP) {
-                const int p = __builtin_amdgcn_readlane(pk, k);
-                yv[u] = readlane_d(b, p);
+                yv[u] = readlane_d(b, k);
                 b = fma(-a[k], yv[u], b);
             }
         }
@@ -496,7 +503,7 @@ __device__ __forceinline__ double lu_solve(const double (&a)[NP], int t, const d
         __builtin_amdgcn_sched_barrier(0);
     }
     wave_sync();
-    b = sv[t >= 0 ? t : 0];
+    b = sv[lane < NP ? lane : 0];
 #pragma unroll
     for (int k0 = NP - 1; k0 >= 0; k0 -= 8) {
         double xv[8];
@@ -504,8 +511,7 @@ __device__ __forceinline__ double lu_solve(const double (&a)[NP], int t, const d
         for (int u = 0; u < 8; ++u) {
             const int k = k0 - u;
             if (k >= 0) {
-                const int p = __builtin_amdgcn_readlane(pk, k);
-                xv[u] = readlane_d(b * dinv, p);
+                xv[u] = readlane_d(b * dinv, k);
                 b = fma(-a[k], xv[u], b);
             }
         }
@@ -552,9 +558,9 @@ __device__ __forceinline__ bool rodas_attempt(const MechDev *__restrict__ M, dou
     double a[NP];
     build_matrix<NP>(M, js.J, 1.0 / (kGamma * h), a);
     js.release();
-    int t, pk;
+    int pk;
     double dinv;
-    const bool ok = lu_factor<NP>(a, t, dinv, pk);
+    const bool ok = lu_factor<NP>(a, dinv, pk);
     if (!ok) return false;
     double u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0, u4 = 0.0, u5 = 0.0, ys = y;
 #pragma unroll 1
@@ -574,7 +580,7 @@ __device__ __forceinline__ bool rodas_attempt(const MechDev *__restrict__ M, dou
             rv += (kRodasC[s][3] / h) * u3;
             rv += (kRodasC[s][4] / h) * u4;
         }
-        const double us = lu_solve<NP>(a, t, dinv, pk, rv, lds + M->off_sv);
+        const double us = lu_solve<NP>(a, dinv, pk, rv, lds + M->off_sv);
         u0 = s == 0 ? us : u0;
         u1 = s == 1 ? us : u1;
         u2 = s == 2 ? us : u2;
@@ -632,7 +638,8 @@ __device__ __forceinline__ double *init_lds(const MechDev *Mp, int jslots, JacSl
     }
     if (lane_id() == 0) {
         lds[M.off_C + M.N] = 1.0;
-        lds[M.off_g + M.N] = 0.0;
+        lds[M.off_g + M.N] = 1.0;
+        lds[M.off_gi + M.N] = 1.0;
         lds[M.off_h + M.N] = 0.0;
     }
     wave_sync();

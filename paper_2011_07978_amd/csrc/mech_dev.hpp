@@ -8,6 +8,7 @@ namespace chem {
 constexpr double RU_J = 8.314462618;   // J/(mol K), for Ea/(R T)
 constexpr double RU_ERG = 8.314462618e7;  // erg/(mol K)
 constexpr double P_ATM = 1.01325e6;    // dyn/cm^2
+constexpr double kLnPatmRu = -4.4074185890025276;   // ln(P_ATM / RU_ERG)
 constexpr int NSEG = 8;                // work-queue segments (one per XCD)
 constexpr int NBUCKET = 32;            // heavy-first cost buckets
 
@@ -126,7 +127,7 @@ struct MechDev {
     int has_fo;             // any fall-off or PLOG reaction
     // per-wavefront LDS region (offsets in doubles); the Jacobian (n rows of
     // stride ldj) has a slot of its own
-    int off_q, off_C, off_g, off_h, off_e, off_cp, off_tb, off_sv, lds_doubles;
+    int off_q, off_C, off_g, off_gi, off_h, off_e, off_cp, off_tb, off_sv, lds_doubles;
 };
 
 struct IntParams {
