@@ -31,9 +31,10 @@ METRIC = "cells·dt/s (53-sp mech): plain vs balanced+surrogate at stated max er
 # HBM bytes per attempted Rodas4 step of k_integrate_queue<54> (FETCH_SIZE x 2
 # + WRITE_SIZE, the factors from a 1 GiB copy), from the counter passes over
 # the headline workload in profiles/k_integrate_queue_54__counters_surrogate_field_1M.md
-# (None: not measured for the current kernel).  Nearly all of it is register
-# spill traffic, proportional to attempted steps.
-TRAFFIC_BYTES_PER_ATTEMPT = 5279.4
+# (None: not measured for the current kernel).  Beyond the cell's own state it
+# is register spill traffic that leaves the caches, proportional to attempted
+# steps.
+TRAFFIC_BYTES_PER_ATTEMPT = 219.35
 
 
 def log(*a):
