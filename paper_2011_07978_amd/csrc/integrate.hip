@@ -183,6 +183,7 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
     const double yw = sp ? y * invWk : 0.0;
     const double sumYW = wave_sum(yw);
     const double rho = p / (RU_ERG * T * sumYW);
+    const double irho = (RU_ERG * T * sumYW) / p;
     const double Ctot = rho * sumYW;
     if (sp) {
         Cl[k] = rho * yw;
@@ -311,10 +312,11 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
     wave_sync();
 
     // species: dY_k/dt = W_k omega_k / rho; dT/dt = -sum_k H_k omega_k / (rho cp)
-    const double fk = sp ? Wk * wl[k] / rho : 0.0;
+    const double fk = sp ? Wk * wl[k] * irho : 0.0;
     const double hs = wave_sum(sp ? hRT * invWk * fk : 0.0);
     const double cps = wave_sum(sp ? y * cpR * invWk : 0.0);
-    const double fT = -T * hs / cps;
+    const double icps = 1.0 / cps;
+    const double fT = -T * hs * icps;
 
     if (JAC) {
         const double cpf = wave_sum(sp ? cpR * invWk * fk : 0.0);
@@ -333,7 +335,7 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
             }
             if (l < N) s0 += (row[1 + l] + tbk) * Cl[l];
             const double s = s0 + s1;
-            const double cst = fk * Wbar - Wk * Wbar * s / rho;
+            const double cst = fk * Wbar - Wk * Wbar * s * irho;
             if (LT) {
                 // 1/W_i from the species records in the shared table (broadcast reads)
 #pragma unroll 8
@@ -344,7 +346,7 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
 #pragma unroll 8
                 for (int i = 0; i < N; ++i) row[1 + i] = iw[i] * (Wk * (row[1 + i] + tbk) + cst);
             }
-            row[0] = Wk / rho * (row[0] - s * invT) + fk * invT;
+            row[0] = Wk * irho * (row[0] - s * invT) + fk * invT;
         }
         wave_sync();
         // temperature row: J_T,c = -(sum_k e_k J_kc)/cp - f_T dcp/dy_c / cp
@@ -359,8 +361,8 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
             if (kk < N) a0 += el[kk] * Jl[(kk + 1) * ldj + lane];
             const double acc = (a0 + a1) * T;
             double v;
-            if (lane == 0) v = -(cpf + acc) / cps - fT * dcps / cps;
-            else v = -acc / cps - fT * cpl[lane - 1] / cps;
+            if (lane == 0) v = -(cpf + acc) * icps - fT * dcps * icps;
+            else v = -acc * icps - fT * cpl[lane - 1] * icps;
             Jl[lane] = v;
         }
         wave_sync();
@@ -562,6 +564,7 @@ __device__ __forceinline__ bool rodas_attempt(const MechDev *__restrict__ M, dou
     double dinv;
     const bool ok = lu_factor<NP>(a, dinv, pk);
     if (!ok) return false;
+    const double hinv = 1.0 / h;
     double u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0, u4 = 0.0, u5 = 0.0, ys = y;
 #pragma unroll 1
     for (int s = 0; s < 6; ++s) {
@@ -574,11 +577,11 @@ __device__ __forceinline__ bool rodas_attempt(const MechDev *__restrict__ M, dou
             ys += kRodasA[s][3] * u3;
             ys += kRodasA[s][4] * u4;
             rv = rhs_eval<false, LT, FO>(M, p, ys, lds, nullptr);
-            rv += (kRodasC[s][0] / h) * u0;
-            rv += (kRodasC[s][1] / h) * u1;
-            rv += (kRodasC[s][2] / h) * u2;
-            rv += (kRodasC[s][3] / h) * u3;
-            rv += (kRodasC[s][4] / h) * u4;
+            rv += (kRodasC[s][0] * hinv) * u0;
+            rv += (kRodasC[s][1] * hinv) * u1;
+            rv += (kRodasC[s][2] * hinv) * u2;
+            rv += (kRodasC[s][3] * hinv) * u3;
+            rv += (kRodasC[s][4] * hinv) * u4;
         }
         const double us = lu_solve<NP>(a, dinv, pk, rv, lds + M->off_sv);
         u0 = s == 0 ? us : u0;
@@ -706,7 +709,7 @@ __device__ __forceinline__ void integrate_cell(const MechDev *__restrict__ M, co
             e = uniform_d(wave_max(r));
         }
         if (!bad && e <= 1.0) {
-            double fac = (e == 0.0) ? 5.0 : fmin(5.0, fmax(0.2, 0.9 * pow(e, -0.25)));
+            double fac = (e == 0.0) ? 5.0 : fmin(5.0, fmax(0.2, 0.9 * rsqrt(sqrt(e))));
             if (rej_last) fac = fmin(fac, 1.0);
             y = ynew;
             t = last ? dt : t + h;
@@ -720,7 +723,7 @@ __device__ __forceinline__ void integrate_cell(const MechDev *__restrict__ M, co
                 jac = true;
             }
         } else {
-            const double fac = bad ? 0.2 : fmax(0.2, 0.9 * pow(e, -0.25));
+            const double fac = bad ? 0.2 : fmax(0.2, 0.9 * rsqrt(sqrt(e)));
             h = uniform_d(h * fac);
             ++nrej;
             rej_last = true;
