@@ -189,15 +189,28 @@ __global__ void k_queue_scan(int *hist, int *n_active) {
     }
 }
 
+// Each workgroup ranks its cells within their buckets in LDS, then reserves
+// one contiguous range per non-empty bucket with a single global atomic, so
+// the global counters see a few adds per workgroup instead of one per cell.
 __global__ __launch_bounds__(MAP_BLOCK) void k_queue_scatter(int64_t ncells, const uint8_t *flags,
                                                              const uint32_t *cost,
                                                              const int *offsets, int *cursor,
                                                              int *queue) {
+    __shared__ int cnt[NBUCKET], base[NBUCKET];
+    if (threadIdx.x < NBUCKET) cnt[threadIdx.x] = 0;
+    __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * MAP_BLOCK + threadIdx.x;
-    if (i >= ncells || (flags && flags[i] >= 2)) return;
-    const int b = cost_bucket(cost, i);
-    const int pos = offsets[b] + atomicAdd(&cursor[b], 1);
-    queue[pos] = (int)i;
+    const bool act = i < ncells && !(flags && flags[i] >= 2);
+    int b = 0, rank = 0;
+    if (act) {
+        b = cost_bucket(cost, i);
+        rank = atomicAdd(&cnt[b], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < NBUCKET && cnt[threadIdx.x] > 0)
+        base[threadIdx.x] = offsets[threadIdx.x] + atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
+    __syncthreads();
+    if (act) queue[base[b] + rank] = (int)i;
 }
 
 // --------------------------------------------------------------- launchers --
