@@ -324,18 +324,19 @@ __device__ bool lu_big(const BigLds &L) {
                     if (v > best) { best = v; bi = r; }   // NaN never wins
                 }
                 const double vmax = wave_max(best);
-                // lowest row among the maxima
-                int cand = best == vmax ? bi : n;
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) cand = min(cand, __shfl_xor(cand, off));
-                if (lane == 0) L.ipiv[k] = cand < n ? cand : k;
-            }
-            __syncthreads();
-            const int pr = L.ipiv[k];
-            if (pr != k && tid < n) {
-                const double t0 = A[(size_t)k * lda + tid];
-                A[(size_t)k * lda + tid] = A[(size_t)pr * lda + tid];
-                A[(size_t)pr * lda + tid] = t0;
+                // lowest row among the maxima: the largest complement
+                const unsigned key = best == vmax && bi < n ? 0xffffffffu - (unsigned)bi : 0u;
+                const unsigned top = wave_max_u32(key);
+                const int pr = top ? (int)(0xffffffffu - top) : k;
+                if (lane == 0) L.ipiv[k] = pr;
+                // the same wavefront swaps the rows: no barrier between
+                // search and swap
+                if (pr != k)
+                    for (int j = lane; j < n; j += 64) {
+                        const double t0 = A[(size_t)k * lda + j];
+                        A[(size_t)k * lda + j] = A[(size_t)pr * lda + j];
+                        A[(size_t)pr * lda + j] = t0;
+                    }
             }
             __syncthreads();
             const double piv = A[(size_t)k * lda + k];
@@ -426,22 +427,35 @@ __device__ double solve_big(const BigLds &L, double b) {
     __syncthreads();
     if (tid < n) v[tid] = z;
     __syncthreads();
-    // forward, unit lower
+    // forward, unit lower.  Wavefront 0 solves the diagonal block with the
+    // block's entries loaded up front (lane r: row kb + r, zero where the
+    // lane takes no update), so only readlane and FMA remain on the chain.
     for (int kb = 0; kb < n; kb += NB) {
         const int jb = min(NB, n - kb), ke = kb + jb;
         if (wv == 0) {
+            const double *rl = A + (size_t)(kb + (lane < jb ? lane : 0)) * lda + kb;
+            double a[NB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) a[q] = (lane > q && lane < jb) ? rl[q] : 0.0;
             double x = lane < jb ? v[kb + lane] : 0.0;
-            for (int q = 0; q < jb; ++q) {
-                const double xq = readlane_d(x, q);
-                if (lane > q && lane < jb) x = fma(-A[(size_t)(kb + lane) * lda + kb + q], xq, x);
-            }
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+                if (q < jb) x = fma(-a[q], readlane_d(x, q), x);
             if (lane < jb) v[kb + lane] = x;
         }
         __syncthreads();
         for (int i = ke + tid; i < n; i += BT) {
             const double *ri = A + (size_t)i * lda + kb;
+            double r[NB], w[NB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                r[q] = q < jb ? ri[q] : 0.0;
+                w[q] = q < jb ? v[kb + q] : 0.0;
+            }
             double s = v[i];
-            for (int q = 0; q < jb; ++q) s = fma(-ri[q], v[kb + q], s);
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+                if (q < jb) s = fma(-r[q], w[q], s);
             v[i] = s;
         }
         __syncthreads();
@@ -451,19 +465,36 @@ __device__ double solve_big(const BigLds &L, double b) {
     for (int kb = last; kb >= 0; kb -= NB) {
         const int jb = min(NB, n - kb);
         if (wv == 0) {
+            // lane r: row kb + r of the diagonal block above the diagonal, and
+            // the reciprocal of its diagonal entry
+            const double *rl = A + (size_t)(kb + (lane < jb ? lane : 0)) * lda + kb;
+            double a[NB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) a[q] = (lane < q && q < jb) ? rl[q] : 0.0;
+            const double dinv = lane < jb ? 1.0 / rl[lane] : 0.0;
             double x = lane < jb ? v[kb + lane] : 0.0;
-            for (int q = jb - 1; q >= 0; --q) {
-                if (lane == q) x = x / A[(size_t)(kb + q) * lda + kb + q];
-                const double xq = readlane_d(x, q);
-                if (lane < q) x = fma(-A[(size_t)(kb + lane) * lda + kb + q], xq, x);
+#pragma unroll
+            for (int q = NB - 1; q >= 0; --q) {
+                if (q < jb) {
+                    const double xq = readlane_d(x * dinv, q);
+                    x = lane == q ? xq : fma(-a[q], xq, x);
+                }
             }
             if (lane < jb) v[kb + lane] = x;
         }
         __syncthreads();
         for (int i = tid; i < kb; i += BT) {
             const double *ri = A + (size_t)i * lda + kb;
+            double r[NB], w[NB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                r[q] = q < jb ? ri[q] : 0.0;
+                w[q] = q < jb ? v[kb + q] : 0.0;
+            }
             double s = v[i];
-            for (int q = 0; q < jb; ++q) s = fma(-ri[q], v[kb + q], s);
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+                if (q < jb) s = fma(-r[q], w[q], s);
             v[i] = s;
         }
         __syncthreads();
