@@ -26,7 +26,8 @@ namespace chem {
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BT = 256;   // threads per cell
-constexpr int NB = 16;    // LU / solve block
+constexpr int NB = 16;    // LU block
+constexpr int SB = 32;    // triangular-solve block
 
 __constant__ double kBigA[6][6] = {
     {0, 0, 0, 0, 0, 0},
@@ -420,61 +421,61 @@ __device__ double solve_big(const BigLds &L, double b) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int n = L.n, lda = L.lda;
     const double *A = L.A;
-    double *v = L.vec;
-    if (tid < n) v[tid] = b;
+    // b in row order in L.vec, the working vector in pivot order in L.w (the
+    // production-rate array, free between RHS evaluations)
+    double *v = L.w;
+    if (tid < n) L.vec[tid] = b;
     __syncthreads();
-    double z = tid < n ? v[L.perm[tid]] : 0.0;
-    __syncthreads();
-    if (tid < n) v[tid] = z;
+    if (tid < n) v[tid] = L.vec[L.perm[tid]];
     __syncthreads();
     // forward, unit lower.  Wavefront 0 solves the diagonal block with the
     // block's entries loaded up front (lane r: row kb + r, zero where the
     // lane takes no update), so only readlane and FMA remain on the chain.
-    for (int kb = 0; kb < n; kb += NB) {
-        const int jb = min(NB, n - kb), ke = kb + jb;
+    for (int kb = 0; kb < n; kb += SB) {
+        const int jb = min(SB, n - kb), ke = kb + jb;
         if (wv == 0) {
             const double *rl = A + (size_t)(kb + (lane < jb ? lane : 0)) * lda + kb;
-            double a[NB];
+            double a[SB];
 #pragma unroll
-            for (int q = 0; q < NB; ++q) a[q] = (lane > q && lane < jb) ? rl[q] : 0.0;
+            for (int q = 0; q < SB; ++q) a[q] = (lane > q && lane < jb) ? rl[q] : 0.0;
             double x = lane < jb ? v[kb + lane] : 0.0;
 #pragma unroll
-            for (int q = 0; q < NB; ++q)
+            for (int q = 0; q < SB; ++q)
                 if (q < jb) x = fma(-a[q], readlane_d(x, q), x);
             if (lane < jb) v[kb + lane] = x;
         }
         __syncthreads();
         for (int i = ke + tid; i < n; i += BT) {
             const double *ri = A + (size_t)i * lda + kb;
-            double r[NB], w[NB];
+            double r[SB], w[SB];
 #pragma unroll
-            for (int q = 0; q < NB; ++q) {
+            for (int q = 0; q < SB; ++q) {
                 r[q] = q < jb ? ri[q] : 0.0;
                 w[q] = q < jb ? v[kb + q] : 0.0;
             }
             double s = v[i];
 #pragma unroll
-            for (int q = 0; q < NB; ++q)
+            for (int q = 0; q < SB; ++q)
                 if (q < jb) s = fma(-r[q], w[q], s);
             v[i] = s;
         }
         __syncthreads();
     }
     // backward, upper
-    const int last = ((n - 1) / NB) * NB;
-    for (int kb = last; kb >= 0; kb -= NB) {
-        const int jb = min(NB, n - kb);
+    const int last = ((n - 1) / SB) * SB;
+    for (int kb = last; kb >= 0; kb -= SB) {
+        const int jb = min(SB, n - kb);
         if (wv == 0) {
             // lane r: row kb + r of the diagonal block above the diagonal, and
             // the reciprocal of its diagonal entry
             const double *rl = A + (size_t)(kb + (lane < jb ? lane : 0)) * lda + kb;
-            double a[NB];
+            double a[SB];
 #pragma unroll
-            for (int q = 0; q < NB; ++q) a[q] = (lane < q && q < jb) ? rl[q] : 0.0;
+            for (int q = 0; q < SB; ++q) a[q] = (lane < q && q < jb) ? rl[q] : 0.0;
             const double dinv = lane < jb ? 1.0 / rl[lane] : 0.0;
             double x = lane < jb ? v[kb + lane] : 0.0;
 #pragma unroll
-            for (int q = NB - 1; q >= 0; --q) {
+            for (int q = SB - 1; q >= 0; --q) {
                 if (q < jb) {
                     const double xq = readlane_d(x * dinv, q);
                     x = lane == q ? xq : fma(-a[q], xq, x);
@@ -485,15 +486,15 @@ __device__ double solve_big(const BigLds &L, double b) {
         __syncthreads();
         for (int i = tid; i < kb; i += BT) {
             const double *ri = A + (size_t)i * lda + kb;
-            double r[NB], w[NB];
+            double r[SB], w[SB];
 #pragma unroll
-            for (int q = 0; q < NB; ++q) {
+            for (int q = 0; q < SB; ++q) {
                 r[q] = q < jb ? ri[q] : 0.0;
                 w[q] = q < jb ? v[kb + q] : 0.0;
             }
             double s = v[i];
 #pragma unroll
-            for (int q = 0; q < NB; ++q)
+            for (int q = 0; q < SB; ++q)
                 if (q < jb) s = fma(-r[q], w[q], s);
             v[i] = s;
         }
