@@ -135,7 +135,14 @@ struct JacSlot {
 // f(y), and with JAC the analytic Jacobian into LDS (row-major, stride ldj).
 // Returns f_r on lane r.  All lanes of the wave must call it.
 // -----------------------------------------------------------------------------
-template <bool JAC, bool LT, bool FO>
+// Species sums: with at most 16 unknowns every species sits in lanes 0..15.
+template <int NP>
+__device__ __forceinline__ double species_sum(double v) {
+    if constexpr (NP <= 16) return wave_sum_row0(v);
+    else return wave_sum(v);
+}
+
+template <int NP, bool JAC, bool LT, bool FO>
 __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const double p,
                                            const double y, double *__restrict__ lds,
                                            double *__restrict__ Jl) {
@@ -181,7 +188,7 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
         invWk = a[15 * fs];
     }
     const double yw = sp ? y * invWk : 0.0;
-    const double sumYW = wave_sum(yw);
+    const double sumYW = species_sum<NP>(yw);
     const double rho = p / (RU_ERG * T * sumYW);
     const double irho = (RU_ERG * T * sumYW) / p;
     const double Ctot = rho * sumYW;
@@ -307,20 +314,22 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
     for (int j = lane; j < R; j += 128) {
         const bool v2 = j + 64 < R;
         reaction(j, true);
-        reaction(v2 ? j + 64 : j, v2);
+        // the masked duplicate only when some lane of the trip has a second
+        // reaction (a skipped duplicate would add zeros)
+        if (__builtin_amdgcn_readfirstlane(j - lane) + 64 < R) reaction(v2 ? j + 64 : j, v2);
     }
     wave_sync();
 
     // species: dY_k/dt = W_k omega_k / rho; dT/dt = -sum_k H_k omega_k / (rho cp)
     const double fk = sp ? Wk * wl[k] * irho : 0.0;
-    const double hs = wave_sum(sp ? hRT * invWk * fk : 0.0);
-    const double cps = wave_sum(sp ? y * cpR * invWk : 0.0);
+    const double hs = species_sum<NP>(sp ? hRT * invWk * fk : 0.0);
+    const double cps = species_sum<NP>(sp ? y * cpR * invWk : 0.0);
     const double icps = 1.0 / cps;
     const double fT = -T * hs * icps;
 
     if (JAC) {
-        const double cpf = wave_sum(sp ? cpR * invWk * fk : 0.0);
-        const double dcps = wave_sum(sp ? y * dcpR * invWk : 0.0);
+        const double cpf = species_sum<NP>(sp ? cpR * invWk * fk : 0.0);
+        const double dcps = species_sum<NP>(sp ? y * dcpR * invWk : 0.0);
         const double Wbar = 1.0 / sumYW;
         // species rows: chain rule from concentrations to (T, Y)
         if (sp) {
@@ -380,6 +389,7 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
 // within a factor 1 + 2^-20 of the largest candidate, ties going to the
 // lowest lane.  A NaN entry sorts above every number and is caught by the
 // reciprocal check after the factorisation.
+template <int NP>
 struct PivotSearch {
     unsigned key, v;
     int p;
@@ -394,11 +404,15 @@ struct PivotSearch {
             case 2: v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xf, 0xf, false)); break;
             case 3: v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xf, 0xf, false)); break;
             case 4: {
-                const unsigned a = max((unsigned)__builtin_amdgcn_readlane((int)v, 0),
-                                       (unsigned)__builtin_amdgcn_readlane((int)v, 16));
-                const unsigned b = max((unsigned)__builtin_amdgcn_readlane((int)v, 32),
-                                       (unsigned)__builtin_amdgcn_readlane((int)v, 48));
-                v = max(a, b);
+                if constexpr (NP <= 16) {   // candidates only in lanes 0..15
+                    v = (unsigned)__builtin_amdgcn_readlane((int)v, 0);
+                } else {
+                    const unsigned a = max((unsigned)__builtin_amdgcn_readlane((int)v, 0),
+                                           (unsigned)__builtin_amdgcn_readlane((int)v, 16));
+                    const unsigned b = max((unsigned)__builtin_amdgcn_readlane((int)v, 32),
+                                           (unsigned)__builtin_amdgcn_readlane((int)v, 48));
+                    v = max(a, b);
+                }
                 break;
             }
             case 5: {
@@ -429,7 +443,7 @@ __device__ __forceinline__ bool lu_factor(double (&a)[NP], double &dinv, int &pk
     const bool active = lane < NP;
     int t = -1;
     dinv = 0.0;
-    PivotSearch ps;
+    PivotSearch<NP> ps;
 #pragma unroll
     for (int s = 0; s < kSearchStages; ++s) ps.stage(s, a[0], active);
 #pragma unroll
@@ -576,7 +590,7 @@ __device__ __forceinline__ bool rodas_attempt(const MechDev *__restrict__ M, dou
             ys += kRodasA[s][2] * u2;
             ys += kRodasA[s][3] * u3;
             ys += kRodasA[s][4] * u4;
-            rv = rhs_eval<false, LT, FO>(M, p, ys, lds, nullptr);
+            rv = rhs_eval<NP, false, LT, FO>(M, p, ys, lds, nullptr);
             rv += (kRodasC[s][0] * hinv) * u0;
             rv += (kRodasC[s][1] * hinv) * u1;
             rv += (kRodasC[s][2] * hinv) * u2;
@@ -686,7 +700,7 @@ __device__ __forceinline__ void integrate_cell(const MechDev *__restrict__ M, co
     // after each matrix build, so a rejected step assembles it again; the
     // same y gives the same bits)
     js.acquire();
-    double f0 = rhs_eval<true, LT, FO>(M, p, y, lds, js.J);
+    double f0 = rhs_eval<NP, true, LT, FO>(M, p, y, lds, js.J);
     bool jac = true;
     while (t < dt) {
         if (nacc + nrej >= P.max_steps) { status = 1; break; }
@@ -695,7 +709,7 @@ __device__ __forceinline__ void integrate_cell(const MechDev *__restrict__ M, co
         if (h < P.hmin_frac * dt) { status = 2; break; }
         if (!jac) {
             js.acquire();
-            f0 = rhs_eval<true, LT, FO>(M, p, y, lds, js.J);
+            f0 = rhs_eval<NP, true, LT, FO>(M, p, y, lds, js.J);
         }
         double ynew = 0.0, ev = 0.0;
         const bool ok = rodas_attempt<NP, LT, FO>(M, p, y, f0, h, lds, js, ynew, ev);
@@ -706,7 +720,8 @@ __device__ __forceinline__ void integrate_cell(const MechDev *__restrict__ M, co
             const double sc = P.atol + P.rtol * fmax(fabs(y), fabs(ynew));
             const double r = lane < n ? fabs(ev) / sc : 0.0;
             bad = wave_any(r != r);
-            e = uniform_d(wave_max(r));
+            if constexpr (NP <= 16) e = uniform_d(wave_max_row0(r));
+            else e = uniform_d(wave_max(r));
         }
         if (!bad && e <= 1.0) {
             double fac = (e == 0.0) ? 5.0 : fmin(5.0, fmax(0.2, 0.9 * rsqrt(sqrt(e))));
@@ -719,7 +734,7 @@ __device__ __forceinline__ void integrate_cell(const MechDev *__restrict__ M, co
             rej_last = false;
             if (t < dt) {
                 js.acquire();
-                f0 = rhs_eval<true, LT, FO>(M, p, y, lds, js.J);
+                f0 = rhs_eval<NP, true, LT, FO>(M, p, y, lds, js.J);
                 jac = true;
             }
         } else {
@@ -829,7 +844,7 @@ __global__ __launch_bounds__(64) void k_eval_rhs_jac(const MechDev *__restrict__
     double y = 0.0;
     if (lane == 0) y = P.T[cell];
     else if (lane <= N) y = P.Y[(int64_t)(lane - 1) * P.ncells + cell];
-    const double f = rhs_eval<true, true, true>(M, P.p[cell], y, lds, js.J);
+    const double f = rhs_eval<NP, true, true, true>(M, P.p[cell], y, lds, js.J);
     if (fout && lane < n) fout[cell * n + lane] = f;
     if (Jout)
         for (int i = lane; i < n * n; i += 64)
@@ -847,7 +862,7 @@ __global__ __launch_bounds__(64) void k_rodas_step(const MechDev *__restrict__ M
     if (lane == 0) y = P.T[cell];
     else if (lane <= N) y = P.Y[(int64_t)(lane - 1) * P.ncells + cell];
     const double p = P.p[cell];
-    const double f0 = rhs_eval<true, true, true>(M, p, y, lds, js.J);
+    const double f0 = rhs_eval<NP, true, true, true>(M, p, y, lds, js.J);
     double ynew = 0.0, err = 0.0;
     const bool ok = rodas_attempt<NP, true, true>(M, p, y, f0, h, lds, js, ynew, err);
     if (!ok) { ynew = NAN; err = NAN; }

@@ -53,6 +53,17 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 __device__ __forceinline__ double max2(double a, double b) { return a > b ? a : b; }
 
+// The same reductions when only lanes 0..15 can hold nonzero values (the
+// other rows would add zeros or maxima of zero): the row-0 result, the same
+// bits as the 64-lane form.
+__device__ __forceinline__ double wave_sum_row0(double v) {
+    v += dpp_d<0xB1>(v);
+    v += dpp_d<0x4E>(v);
+    v += dpp_d<0x141>(v);
+    v += dpp_d<0x140>(v);
+    return readlane_d(v, 0);
+}
+
 // Maximum of values that are not NaN.
 __device__ __forceinline__ double wave_max(double v) {
     v = max2(v, dpp_d<0xB1>(v));
@@ -60,6 +71,14 @@ __device__ __forceinline__ double wave_max(double v) {
     v = max2(v, dpp_d<0x141>(v));
     v = max2(v, dpp_d<0x140>(v));
     return max2(max2(readlane_d(v, 0), readlane_d(v, 16)), max2(readlane_d(v, 32), readlane_d(v, 48)));
+}
+
+__device__ __forceinline__ double wave_max_row0(double v) {
+    v = max2(v, dpp_d<0xB1>(v));
+    v = max2(v, dpp_d<0x4E>(v));
+    v = max2(v, dpp_d<0x141>(v));
+    v = max2(v, dpp_d<0x140>(v));
+    return readlane_d(v, 0);
 }
 
 // Maximum of unsigned 32-bit keys (every lane returns the same value).
