@@ -14,7 +14,8 @@
 //     and the chain rule from concentrations to (T, Y) on the Jacobian rows;
 //   - LU with partial pivoting, row-per-lane in registers: lane r holds row r
 //     of M = I/(gamma h) - J; the pivot row is broadcast with readlane and no
-//     row is moved, each lane only remembers at which step it became pivot;
+//     row moves while factorising (a lane remembers at which step it became
+//     pivot); at the end the rows are put in pivot order;
 //   - triangular solves follow the same layout.
 // The cell's arithmetic does not depend on which workgroup runs it, so the
 // static launch and the work-queue launch give bit-identical results.
