@@ -25,7 +25,8 @@ class StepCost:
     F_lu: int           # LU with partial pivoting, n x n
     F_solve: int        # forward + backward substitution
     F_stage: int        # Rodas4 stage combinations, error norm
-    X_rhs: int          # transcendentals per f(y)
+    X_rhs: int          # transcendentals per f(y): exp for each k_f, exp(g_k) and its
+                        # inverse for each species (the K_c factors), ln T
 
     @property
     def F_attempt(self):
@@ -71,7 +72,7 @@ def step_cost(mech) -> StepCost:
     F_lu = (n - 1) * n // 2 + (n - 1) * n * (2 * n - 1) // 3
     F_solve = 2 * n * n - n
     return StepCost(n=n, F_rhs=F_rhs, F_jac=F_jac, F_build=n * n, F_lu=F_lu, F_solve=F_solve,
-                    F_stage=65 * n, X_rhs=2 * R + 2)
+                    F_stage=65 * n, X_rhs=R + 2 * N + 1)
 
 
 def state_bytes(mech) -> int:
