@@ -304,119 +304,123 @@ __device__ double rhs_big(const MechDev *__restrict__ Mp, const double p, const 
 }
 
 // -----------------------------------------------------------------------------
-// LU of L.A (n x n) with partial pivoting (ties to the lowest row), rows
-// swapped in place; L.ipiv[k] = row swapped with k at step k, L.perm[i] = the
-// original row now at position i.  Returns false if a pivot is zero or not
-// finite.
+// LU of L.A (n x n) with partial pivoting, thread i owning physical row i.
+// Rows never move: step k's pivot is the free row with the largest |a_ik|
+// (upper 48 bits of |a|, ties to the lowest row), found by an LDS 64-bit
+// atomic maximum while the rows update the previous column, so each step
+// costs one barrier.  On return L.perm[k] = the physical row of step k (its
+// L part in columns before k, its U part from k on).  Returns false if a
+// pivot is zero or not finite.
 // -----------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long pivot_key(double v, int row) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(fabs(v));
+    return ((b >> 16) << 16) | (unsigned long long)(0xffff - row);
+}
+__device__ __forceinline__ void key_max(unsigned long long *p, unsigned long long v) {
+    __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 __device__ bool lu_big(const BigLds &L) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int n = L.n, lda = L.lda;
     double *A = L.A;
+    int *prow = L.perm, *rem = L.ipiv;
+    unsigned long long *slot = reinterpret_cast<unsigned long long *>(L.vec);   // one per column
+    int *nrem = reinterpret_cast<int *>(L.red + 12);
     bool ok = true;
+    bool free_row = tid < n;   // this thread's row has not been pivot yet
+    for (int i = tid; i < n; i += BT) slot[i] = 0ull;
+    __syncthreads();
+    if (free_row) key_max(&slot[0], pivot_key(A[(size_t)tid * lda], tid));
+    __syncthreads();
     for (int kb = 0; kb < n; kb += NB) {
         const int jb = min(NB, n - kb), ke = kb + jb;
         for (int k = kb; k < ke; ++k) {
-            if (wv == 0) {
-                double best = -1.0;
-                int bi = n;
-                for (int r = k + lane; r < n; r += 64) {
-                    const double v = fabs(A[(size_t)r * lda + k]);
-                    if (v > best) { best = v; bi = r; }   // NaN never wins
-                }
-                const double vmax = wave_max(best);
-                // lowest row among the maxima: the largest complement
-                const unsigned key = best == vmax && bi < n ? 0xffffffffu - (unsigned)bi : 0u;
-                const unsigned top = wave_max_u32(key);
-                const int pr = top ? (int)(0xffffffffu - top) : k;
-                if (lane == 0) L.ipiv[k] = pr;
-                // the same wavefront swaps the rows: no barrier between
-                // search and swap
-                if (pr != k)
-                    for (int j = lane; j < n; j += 64) {
-                        const double t0 = A[(size_t)k * lda + j];
-                        A[(size_t)k * lda + j] = A[(size_t)pr * lda + j];
-                        A[(size_t)pr * lda + j] = t0;
-                    }
-            }
-            __syncthreads();
-            const double piv = A[(size_t)k * lda + k];
+            const int pr = 0xffff - (int)(slot[k] & 0xffffull);
+            if (tid == 0) prow[k] = pr;
+            const double *rp = A + (size_t)pr * lda;
+            const double piv = rp[k];
             if (!(fabs(piv) > 0.0) || !(fabs(piv) < INFINITY)) ok = false;
             const double rinv = 1.0 / piv;
-            for (int i = k + 1 + tid; i < n; i += BT) {
-                double *ri = A + (size_t)i * lda;
+            if (tid == pr) free_row = false;
+            if (free_row) {
+                double *ri = A + (size_t)tid * lda;
                 const double l = ri[k] * rinv;
                 ri[k] = l;
-                for (int j = k + 1; j < ke; ++j) ri[j] = fma(-l, A[(size_t)k * lda + j], ri[j]);
+                for (int j = k + 1; j < ke; ++j) ri[j] = fma(-l, rp[j], ri[j]);
+                if (k + 1 < ke) key_max(&slot[k + 1], pivot_key(ri[k + 1], tid));
             }
             __syncthreads();
         }
         if (ke < n) {
-            // block row of U: U12 = L11^-1 A12, one thread per column
+            // block row of U: U12 = L11^-1 A12 on the block's pivot rows, one
+            // thread per column; the remaining rows are listed for the update
+            if (tid == 0) *nrem = 0;
+            int pq[NB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) pq[q] = q < jb ? prow[kb + q] : 0;
             for (int j = ke + tid; j < n; j += BT) {
                 double x[NB];
 #pragma unroll
-                for (int q = 0; q < NB; ++q) x[q] = q < jb ? A[(size_t)(kb + q) * lda + j] : 0.0;
+                for (int q = 0; q < NB; ++q) x[q] = q < jb ? A[(size_t)pq[q] * lda + j] : 0.0;
 #pragma unroll
                 for (int r = 1; r < NB; ++r) {
                     if (r < jb) {
                         double s = x[r];
 #pragma unroll
-                        for (int q = 0; q < r; ++q) s = fma(-A[(size_t)(kb + r) * lda + kb + q], x[q], s);
+                        for (int q = 0; q < r; ++q) s = fma(-A[(size_t)pq[r] * lda + kb + q], x[q], s);
                         x[r] = s;
                     }
                 }
 #pragma unroll
                 for (int q = 1; q < NB; ++q)
-                    if (q < jb) A[(size_t)(kb + q) * lda + j] = x[q];
+                    if (q < jb) A[(size_t)pq[q] * lda + j] = x[q];
             }
             __syncthreads();
-            // trailing update A22 -= L21 U12 on the matrix cores, 16 x 16 tiles
+            if (free_row) rem[__hip_atomic_fetch_add(nrem, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)] = tid;
+            __syncthreads();
+            // trailing update A22 -= L21 U12 on the matrix cores, 16 x 16
+            // tiles over the listed rows (each row's result does not depend
+            // on its tile or position)
             const int m = n - ke, tiles = (m + 15) >> 4;
             const int lr = lane & 15, lk = lane >> 4;
             for (int t = wv; t < tiles * tiles; t += 4) {
-                const int r0 = ke + 16 * (t / tiles), c0 = ke + 16 * (t % tiles);
+                const int r0 = 16 * (t / tiles), c0 = ke + 16 * (t % tiles);
                 const int col = c0 + lr;
                 f64x4 acc;
                 // v_mfma_f64_16x16x4f64: lane l holds A[l % 16][l / 16], B[l / 16][l % 16]
                 // and D[l / 16 + 4 i][l % 16], i = 0..3 (checked on gfx950)
+                int drow[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int row = r0 + lk + 4 * i;
-                    acc[i] = (row < n && col < n) ? A[(size_t)row * lda + col] : 0.0;
+                    const int rr = r0 + lk + 4 * i;
+                    drow[i] = rr < m ? rem[rr] : -1;
+                    acc[i] = (drow[i] >= 0 && col < n) ? A[(size_t)drow[i] * lda + col] : 0.0;
                 }
+                const int ar = r0 + lr;
+                const int arow = ar < m ? rem[ar] : -1;
 #pragma unroll
                 for (int ks = 0; ks < NB / 4; ++ks) {
                     const int kk = kb + 4 * ks + lk;
-                    const int arow = r0 + lr;
-                    const double a = (arow < n && kk < ke) ? -A[(size_t)arow * lda + kk] : 0.0;
-                    const double b = (col < n && kk < ke) ? A[(size_t)kk * lda + col] : 0.0;
+                    const double a = (arow >= 0 && kk < ke) ? -A[(size_t)arow * lda + kk] : 0.0;
+                    const double b = (col < n && kk < ke) ? A[(size_t)prow[kk] * lda + col] : 0.0;
                     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
                 }
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int row = r0 + lk + 4 * i;
-                    if (row < n && col < n) A[(size_t)row * lda + col] = acc[i];
-                }
+                for (int i = 0; i < 4; ++i)
+                    if (drow[i] >= 0 && col < n) A[(size_t)drow[i] * lda + col] = acc[i];
             }
+            __syncthreads();
+            // the next block's first pivot
+            if (free_row) key_max(&slot[ke], pivot_key(A[(size_t)tid * lda + ke], tid));
             __syncthreads();
         }
     }
-    // composed row permutation
-    if (tid == 0) {
-        for (int i = 0; i < n; ++i) L.perm[i] = i;
-        for (int k = 0; k < n; ++k) {
-            const int pr = L.ipiv[k];
-            const int t0 = L.perm[k];
-            L.perm[k] = L.perm[pr];
-            L.perm[pr] = t0;
-        }
-    }
-    __syncthreads();
     return ok;
 }
 
-// Solve (L U) x = P b; thread i passes b_i and receives x_i.
+// Solve (L U) x = P b with the factors of lu_big (logical row k in physical
+// row L.perm[k]); thread i passes b_i and receives x_i.
 __device__ double solve_big(const BigLds &L, double b) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int n = L.n, lda = L.lda;
@@ -434,7 +438,7 @@ __device__ double solve_big(const BigLds &L, double b) {
     for (int kb = 0; kb < n; kb += SB) {
         const int jb = min(SB, n - kb), ke = kb + jb;
         if (wv == 0) {
-            const double *rl = A + (size_t)(kb + (lane < jb ? lane : 0)) * lda + kb;
+            const double *rl = A + (size_t)L.perm[kb + (lane < jb ? lane : 0)] * lda + kb;
             double a[SB];
 #pragma unroll
             for (int q = 0; q < SB; ++q) a[q] = (lane > q && lane < jb) ? rl[q] : 0.0;
@@ -446,7 +450,7 @@ __device__ double solve_big(const BigLds &L, double b) {
         }
         __syncthreads();
         for (int i = ke + tid; i < n; i += BT) {
-            const double *ri = A + (size_t)i * lda + kb;
+            const double *ri = A + (size_t)L.perm[i] * lda + kb;
             double r[SB], w[SB];
 #pragma unroll
             for (int q = 0; q < SB; ++q) {
@@ -468,7 +472,7 @@ __device__ double solve_big(const BigLds &L, double b) {
         if (wv == 0) {
             // lane r: row kb + r of the diagonal block above the diagonal, and
             // the reciprocal of its diagonal entry
-            const double *rl = A + (size_t)(kb + (lane < jb ? lane : 0)) * lda + kb;
+            const double *rl = A + (size_t)L.perm[kb + (lane < jb ? lane : 0)] * lda + kb;
             double a[SB];
 #pragma unroll
             for (int q = 0; q < SB; ++q) a[q] = (lane < q && q < jb) ? rl[q] : 0.0;
@@ -485,7 +489,7 @@ __device__ double solve_big(const BigLds &L, double b) {
         }
         __syncthreads();
         for (int i = tid; i < kb; i += BT) {
-            const double *ri = A + (size_t)i * lda + kb;
+            const double *ri = A + (size_t)L.perm[i] * lda + kb;
             double r[SB], w[SB];
 #pragma unroll
             for (int q = 0; q < SB; ++q) {
