@@ -381,34 +381,50 @@ __device__ bool lu_big(const BigLds &L) {
             __syncthreads();
             // trailing update A22 -= L21 U12 on the matrix cores, 16 x 16
             // tiles over the listed rows (each row's result does not depend
-            // on its tile or position)
+            // on its tile or position).  A wavefront takes whole rows of
+            // tiles: their rows and L21 operands are loaded once, then it
+            // walks the column tiles.
             const int m = n - ke, tiles = (m + 15) >> 4;
             const int lr = lane & 15, lk = lane >> 4;
-            for (int t = wv; t < tiles * tiles; t += 4) {
-                const int r0 = 16 * (t / tiles), c0 = ke + 16 * (t % tiles);
-                const int col = c0 + lr;
-                f64x4 acc;
-                // v_mfma_f64_16x16x4f64: lane l holds A[l % 16][l / 16], B[l / 16][l % 16]
-                // and D[l / 16 + 4 i][l % 16], i = 0..3 (checked on gfx950)
+            int brow[NB / 4];
+#pragma unroll
+            for (int ks = 0; ks < NB / 4; ++ks) {
+                const int kk = kb + 4 * ks + lk;
+                brow[ks] = kk < ke ? prow[kk] : -1;
+            }
+            for (int rt = wv; rt < tiles; rt += 4) {
+                const int r0 = 16 * rt;
                 int drow[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int rr = r0 + lk + 4 * i;
                     drow[i] = rr < m ? rem[rr] : -1;
-                    acc[i] = (drow[i] >= 0 && col < n) ? A[(size_t)drow[i] * lda + col] : 0.0;
                 }
                 const int ar = r0 + lr;
                 const int arow = ar < m ? rem[ar] : -1;
+                // v_mfma_f64_16x16x4f64: lane l holds A[l % 16][l / 16], B[l / 16][l % 16]
+                // and D[l / 16 + 4 i][l % 16], i = 0..3 (checked on gfx950)
+                double a[NB / 4];
 #pragma unroll
                 for (int ks = 0; ks < NB / 4; ++ks) {
                     const int kk = kb + 4 * ks + lk;
-                    const double a = (arow >= 0 && kk < ke) ? -A[(size_t)arow * lda + kk] : 0.0;
-                    const double b = (col < n && kk < ke) ? A[(size_t)prow[kk] * lda + col] : 0.0;
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+                    a[ks] = (arow >= 0 && kk < ke) ? -A[(size_t)arow * lda + kk] : 0.0;
                 }
+                for (int ct = 0; ct < tiles; ++ct) {
+                    const int col = ke + 16 * ct + lr;
+                    f64x4 acc;
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    if (drow[i] >= 0 && col < n) A[(size_t)drow[i] * lda + col] = acc[i];
+                    for (int i = 0; i < 4; ++i)
+                        acc[i] = (drow[i] >= 0 && col < n) ? A[(size_t)drow[i] * lda + col] : 0.0;
+#pragma unroll
+                    for (int ks = 0; ks < NB / 4; ++ks) {
+                        const double b = (col < n && brow[ks] >= 0) ? A[(size_t)brow[ks] * lda + col] : 0.0;
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], b, acc, 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (drow[i] >= 0 && col < n) A[(size_t)drow[i] * lda + col] = acc[i];
+                }
             }
             __syncthreads();
             // the next block's first pivot
