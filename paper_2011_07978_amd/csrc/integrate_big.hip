@@ -27,7 +27,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BT = 256;   // threads per cell
 constexpr int NB = 16;    // LU block
-constexpr int SB = 32;    // triangular-solve block
+constexpr int SB = 16;    // triangular-solve block
 
 __constant__ double kBigA[6][6] = {
     {0, 0, 0, 0, 0, 0},
