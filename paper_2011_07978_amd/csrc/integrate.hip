@@ -308,17 +308,11 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
             }
         }
     };
-    // two reactions per trip, both evaluated unconditionally (the second is a
-    // masked duplicate past the end), so their load, exp and LDS latencies
-    // overlap
+    // one reaction per lane and trip: with two wavefronts per SIMD the other
+    // wavefront covers this one's load, exp and LDS latencies, and the
+    // smaller loop body keeps registers free
 #pragma unroll 1
-    for (int j = lane; j < R; j += 128) {
-        const bool v2 = j + 64 < R;
-        reaction(j, true);
-        // the masked duplicate only when some lane of the trip has a second
-        // reaction (a skipped duplicate would add zeros)
-        if (__builtin_amdgcn_readfirstlane(j - lane) + 64 < R) reaction(v2 ? j + 64 : j, v2);
-    }
+    for (int j = lane; j < R; j += 64) reaction(j, true);
     wave_sync();
 
     // species: dY_k/dt = W_k omega_k / rho; dT/dt = -sum_k H_k omega_k / (rho cp)
