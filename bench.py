@@ -34,7 +34,7 @@ METRIC = "cells·dt/s (53-sp mech): plain vs balanced+surrogate at stated max er
 # (None: not measured for the current kernel).  Beyond the cell's own state it
 # is register spill traffic that leaves the caches, proportional to attempted
 # steps.
-TRAFFIC_BYTES_PER_ATTEMPT = 137.72
+TRAFFIC_BYTES_PER_ATTEMPT = 128.36
 
 
 def log(*a):

@@ -149,12 +149,15 @@ __device__ __forceinline__ double rhs_eval(const MechDev *__restrict__ Mp, const
                                            double *__restrict__ Jl) {
     // The memory clobber keeps the descriptor loads, and the opaque lane index
     // every per-lane address, local to this call instead of being hoisted out
-    // of the step loop and held in registers across it.
+    // of the step loop and held in registers across it.  The sizes are made
+    // opaque too: the trip counts and strides derived from them are then
+    // formed here rather than held (spilled) across the step loop.
     asm volatile("" ::: "memory");
     int lane = lane_id();
     asm volatile("" : "+v"(lane));
     const MechDev &M = *Mp;
-    const int N = M.N, R = M.R, n = M.n, ldj = M.ldj;
+    int N = M.N, R = M.R, n = M.n, ldj = M.ldj;
+    asm volatile("" : "+s"(N), "+s"(R), "+s"(n), "+s"(ldj));
     double *__restrict__ wl = lds + M.off_q;    // production rates omega_k (+ sentinel)
     double *__restrict__ Cl = lds + M.off_C;
     double *__restrict__ gl = lds + M.off_g;
@@ -389,7 +392,8 @@ struct PivotSearch {
     unsigned key, v;
     int p;
     double piv, r, e;
-    __device__ __forceinline__ void stage(int s, double col, bool cand) {
+    // cand: this lane's row may be pivot; candm: the same as a scalar lane mask
+    __device__ __forceinline__ void stage(int s, double col, bool cand, unsigned long long candm) {
         switch (s) {
             case 0:
                 key = cand ? ((unsigned)__double2hiint(col) & 0x7fffffffu) : 0u;
@@ -402,16 +406,17 @@ struct PivotSearch {
                 if constexpr (NP <= 16) {   // candidates only in lanes 0..15
                     v = (unsigned)__builtin_amdgcn_readlane((int)v, 0);
                 } else {
-                    const unsigned a = max((unsigned)__builtin_amdgcn_readlane((int)v, 0),
-                                           (unsigned)__builtin_amdgcn_readlane((int)v, 16));
-                    const unsigned b = max((unsigned)__builtin_amdgcn_readlane((int)v, 32),
-                                           (unsigned)__builtin_amdgcn_readlane((int)v, 48));
-                    v = max(a, b);
+                    // each 16-lane row holds its maximum; row broadcasts fold
+                    // row 0 into row 1 and row 2 into row 3, then rows 0-1 into
+                    // rows 2-3, so lane 63 holds the maximum of the wavefront
+                    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));
+                    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));
+                    v = (unsigned)__builtin_amdgcn_readlane((int)v, 63);
                 }
                 break;
             }
             case 5: {
-                const unsigned long long bal = __ballot(cand && key == v);
+                const unsigned long long bal = ballot(key == v) & candm;
                 p = bal ? (int)__builtin_ctzll(bal) : 0;
                 break;
             }
@@ -438,18 +443,23 @@ __device__ __forceinline__ bool lu_factor(double (&a)[NP], double &dinv, int &pk
     const bool active = lane < NP;
     int t = -1;
     dinv = 0.0;
+    // rows not yet pivot, as a scalar lane mask: the per-lane tests below
+    // read it directly instead of comparing vector registers
+    unsigned long long rem = NP >= 64 ? ~0ull : (1ull << NP) - 1ull;
     PivotSearch<NP> ps;
 #pragma unroll
-    for (int s = 0; s < kSearchStages; ++s) ps.stage(s, a[0], active);
+    for (int s = 0; s < kSearchStages; ++s) ps.stage(s, a[0], active, rem);
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
         const int p = ps.p;
         const double rinv = ps.r;
-        if (lane == p) {
+        const unsigned long long pm = 1ull << p;
+        if (__builtin_amdgcn_inverse_ballot_w64(pm)) {
             t = k;
             dinv = rinv;
         }
-        const bool upd = active && t < 0;
+        rem &= ~pm;
+        const bool upd = __builtin_amdgcn_inverse_ballot_w64(rem);
         const double l = upd ? a[k] * rinv : 0.0;
         if (upd) a[k] = l;
         // column k + 1 first: the next pivot search starts from it and runs
@@ -460,7 +470,7 @@ __device__ __forceinline__ bool lu_factor(double (&a)[NP], double &dinv, int &pk
             const double pj = readlane_d(a[j], p);
             a[j] = fma(-l, pj, a[j]);
             if (j == k + 1 || (j - k - 1) % kColsPerStage == 0) {
-                if (stage < kSearchStages) ps.stage(stage, a[k + 1], upd);
+                if (stage < kSearchStages) ps.stage(stage, a[k + 1], upd, rem);
                 ++stage;
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -468,7 +478,7 @@ __device__ __forceinline__ bool lu_factor(double (&a)[NP], double &dinv, int &pk
         if (k + 1 < NP) {
 #pragma unroll
             for (int s = 0; s < kSearchStages; ++s)
-                if (s >= stage) ps.stage(s, a[k + 1], upd);
+                if (s >= stage) ps.stage(s, a[k + 1], upd, rem);
         }
         __builtin_amdgcn_sched_barrier(0);
     }
@@ -541,15 +551,35 @@ __device__ __forceinline__ double lu_solve(const double (&a)[NP], const double d
 
 template <int NP>
 __device__ __forceinline__ void build_matrix(const MechDev *__restrict__ Mp,
-                                             const double *__restrict__ J, double diag,
+                                             double *__restrict__ J, double diag,
                                              double (&a)[NP]) {
     asm volatile("" ::: "memory");
     const MechDev &M = *Mp;
     int lane = lane_id();
     asm volatile("" : "+v"(lane));
-    const int n = M.n;
+    // n is made opaque here so that the per-column tests of the general case
+    // are formed at each build: hoisted out of the step loop they held some
+    // 160 scalar registers, spilled to vector lanes and read back each attempt
+    int n = M.n;
+    asm volatile("" : "+s"(n));
     const bool row_ok = lane < n;
-    const double *Jl = J + (row_ok ? lane : 0) * M.ldj;
+    double *Jl = J + (row_ok ? lane : 0) * M.ldj;
+    if (n == NP) {
+        // every row and column is the mechanism's.  The diagonal is shifted in
+        // place (x - diag, then negated, rounds as diag - x) and put back
+        // after the reads, so the columns need no per-lane test; rows past
+        // the matrix get zeros.
+        double d = 0.0;
+        if (row_ok) {
+            d = Jl[lane];
+            Jl[lane] = d - diag;
+        }
+        const double sc = row_ok ? -1.0 : 0.0;
+#pragma unroll
+        for (int c = 0; c < NP; ++c) a[c] = Jl[c] * sc;
+        if (row_ok) Jl[lane] = d;
+        return;
+    }
 #pragma unroll
     for (int c = 0; c < NP; ++c) {
         const double x = Jl[c < n ? c : 0];

@@ -39,16 +39,29 @@ __device__ __forceinline__ double dpp_d(double v) {
     return __hiloint2double(hi, lo);
 }
 
+// Row broadcasts (GFX9 DPP): 0x142 row_bcast:15 hands lane 15 of each row to
+// the next row, 0x143 row_bcast:31 hands lane 31 to rows 2 and 3; rows left
+// out by the row mask receive 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_bcast_d(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
 // Reductions over the 64 lanes.  Within each 16-lane row the two operands of
 // every combine are the same pair of values on both lanes (sum and max
-// commute), then the four row results are combined in a fixed order; every
-// lane therefore returns the same bits, independent of scheduling.
+// commute), so every lane of a row holds the same row result; the row results
+// are then combined as (r0 + r1) + (r2 + r3) by two row broadcasts, the sum
+// read from lane 63.  The bits do not depend on scheduling.
 __device__ __forceinline__ double wave_sum(double v) {
     v += dpp_d<0xB1>(v);
     v += dpp_d<0x4E>(v);
     v += dpp_d<0x141>(v);
     v += dpp_d<0x140>(v);
-    return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+    v += dpp_bcast_d<0x142, 0xa>(v);   // rows 1, 3: r1 + r0, r3 + r2
+    v += dpp_bcast_d<0x143, 0xc>(v);   // rows 2, 3: + lane 31 (r1 + r0)
+    return readlane_d(v, 63);
 }
 
 __device__ __forceinline__ double max2(double a, double b) { return a > b ? a : b; }
@@ -104,6 +117,9 @@ __device__ __forceinline__ double recip_nr(double x) {
     return fma(r, e, r);
 }
 
-__device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
+// Lane mask of p (the compiler's own mask, with no detour through an integer).
+__device__ __forceinline__ unsigned long long ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+__device__ __forceinline__ bool wave_any(bool p) { return ballot(p) != 0ull; }
 
 }  // namespace chem
