@@ -1,13 +1,17 @@
 """Host code under AddressSanitizer and UndefinedBehaviorSanitizer (CPU only).
 
 The oracle's C sources and the host load-balancing planner (csrc/balance.cpp)
-are compiled with gcc / g++ -fsanitize=address,undefined, every finding fatal,
-together with small drivers (tests/sanitize/) that call each entry point on
-small synthetic inputs.  A driver must exit cleanly, and the values it prints
-must equal those of the regular builds (the oracle through its ctypes
-binding, the planner through the library), which shows that the sanitized
-runs went through the same paths.  No GPU code is built here.
+are compiled with gcc / g++ -fsanitize=address,undefined, and the host side of
+csrc/api.cpp (for its mechanism check) with the same sanitizers through
+-Xarch_host, every finding fatal, together with small drivers
+(tests/sanitize/) that call each entry point on small synthetic inputs.  A
+driver must exit cleanly, and the values it prints must equal those of the
+regular builds (the oracle through its ctypes binding, the planner and the
+mechanism check through the library), which shows that the sanitized runs
+went through the same paths.  No GPU code is built with a sanitizer, and
+nothing here runs on a GPU.
 """
+import copy
 import os
 import subprocess
 
@@ -199,3 +203,98 @@ def test_planner_clean_under_sanitizers(drivers):
         ops, after = chem.plan_balance(n_prob, cost, mf)
         assert got["ops"] == ops
         assert got["loads"] == list(after)
+
+
+# ------------------------------------------------ the library's mechanism check
+def _write_desc(path, mech):
+    R = mech.n_reactions
+    fo_t = getattr(mech, "falloff", None)
+    pl_n = getattr(mech, "plog_count", None)
+    i32 = lambda a: np.ascontiguousarray(a, np.int32).tobytes()
+    f64 = lambda a: np.ascontiguousarray(a, np.float64).tobytes()
+    with open(path, "wb") as f:
+        f.write(i32([mech.n_elements, mech.n_species, R, len(mech.eff_value),
+                     int(fo_t is not None), int(pl_n is not None)]))
+        f.write(f64(mech.elem_mass) + i32(mech.composition) + f64(mech.W) + f64(mech.nasa))
+        f.write(i32(mech.reactants) + i32(mech.products) + f64(mech.A) + f64(mech.b) + f64(mech.Ea))
+        f.write(i32(mech.third_body) + i32(mech.eff_reaction) + i32(mech.eff_species))
+        f.write(f64(mech.eff_value))
+        if fo_t is not None:
+            f.write(i32(fo_t) + f64(mech.fo_params))
+        if pl_n is not None:
+            f.write(i32(pl_n) + f64(mech.plog_params))
+
+
+def _broken(m, **kw):
+    b = copy.deepcopy(m)
+    for k, v in kw.items():
+        setattr(b, k, v)
+    return b
+
+
+def test_mechanism_check_clean_under_sanitizers(tmp_path):
+    from paper_2011_07978_amd import chem
+    try:
+        chem.load_library()
+    except RuntimeError:
+        pytest.skip("libchem.so not built")
+    bdir = os.path.join(REPO, "paper_2011_07978_amd", "_build")
+    others = [os.path.join(bdir, f) for f in ("balance.cpp.o", "integrate.hip.o",
+                                              "integrate_fo.hip.o", "integrate_big.hip.o",
+                                              "map_queue.hip.o", "mlp.hip.o")]
+    if not all(os.path.exists(o) for o in others):
+        pytest.skip("library objects not built")
+    rocm = "/opt/rocm"
+    api_o, drv_o, exe = str(tmp_path / "api_san.o"), str(tmp_path / "drv.o"), str(tmp_path / "vd")
+    host_san = []
+    for flag in SAN[:3]:
+        host_san += ["-Xarch_host", flag]
+    _compile([f"{rocm}/bin/hipcc", "-x", "hip", "-std=c++17", "-O1", "-g", "-fPIC",
+              "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+              "-Wno-unused-command-line-argument"] + host_san +
+             ["-c", os.path.join(REPO, "paper_2011_07978_amd", "csrc", "api.cpp"), "-o", api_o])
+    clang = f"{rocm}/llvm/bin/clang++"
+    _compile([clang, "-std=c++17", "-O1", "-g"] + SAN[:3] +
+             ["-c", os.path.join(HERE, "sanitize", "validate_driver.cpp"), "-o", drv_o])
+    _compile([clang] + SAN[:3] + ["-o", exe, drv_o, api_o] + others +
+             [f"-L{rocm}/lib", "-lamdhip64", f"-Wl,-rpath,{rocm}/lib"])
+
+    base = synth.mechanism("mech53")
+    fo, pl = synth.mechanism("mech53fo"), synth.mechanism("mech53pl")
+    prod = base.products.copy()
+    k = int(prod[17, 0])
+    prod[17, 0] = next(q for q in range(base.n_species)
+                       if not np.array_equal(base.composition[q], base.composition[k]))
+    W = base.W.copy()
+    W[5] *= 1.0 + 1e-6
+    nasa = base.nasa.copy()
+    nasa[3, 1] = -1e-2
+    A = base.A.copy()
+    A[9] = 0.0
+    rea = base.reactants.copy()
+    rea[3, 0] = base.n_species
+    er = base.eff_reaction.copy()
+    er[0] = int(np.nonzero(base.third_body == 0)[0][0])
+    t = fo.falloff.copy()
+    t[int(np.nonzero(fo.third_body == 0)[0][0])] = 2
+    j = int(np.nonzero(pl.plog_count)[0][0])
+    Pp = pl.plog_params.copy()
+    Pp[j, 1, 0] = Pp[j, 0, 0]
+    cases = [synth.mechanism("small"), base, fo, pl, synth.mechanism("mech130"),
+             _broken(base, products=prod), _broken(base, W=W), _broken(base, nasa=nasa),
+             _broken(base, A=A), _broken(base, reactants=rea), _broken(base, eff_reaction=er),
+             _broken(fo, falloff=t), _broken(pl, plog_params=Pp)]
+    paths = []
+    for i, m in enumerate(cases):
+        paths.append(str(tmp_path / f"m{i}.bin"))
+        _write_desc(paths[-1], m)
+    r = subprocess.run([exe] + paths, capture_output=True, text=True, env=_env(), timeout=300)
+    assert r.returncode == 0, r.stderr[-4000:]
+    for bad in ("ERROR: AddressSanitizer", "ERROR: LeakSanitizer", "runtime error:"):
+        assert bad not in r.stderr, r.stderr[-4000:]
+    lines = r.stdout.splitlines()
+    assert len(lines) == len(cases)
+    for m, line in zip(cases, lines):
+        rc, why = chem.validate_mechanism(m)
+        assert line == f"rc {rc} {why}"
+    assert [int(l.split()[1]) for l in lines] == [0] * 5 + [-7] * 8
