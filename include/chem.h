@@ -309,7 +309,8 @@ int chem_integrate_noalloc(chem_ctx *ctx, int64_t n_cells, double *T, const doub
                            double dt, const uint8_t *flags, const int64_t *ref_index, double *h,
                            uint32_t *cost, uint8_t *status, int32_t *steps, chem_stats *stats);
 
-/* chem_integrate with the learned surrogate first: every cell whose flag is
+/* chem_integrate with the learned surrogate first (not in the paper; the
+ * learned relative of the tabulation methods of Sec. 1 and Sec. 5): every cell whose flag is
  * CHEM_FLAG_SOLVE is offered to the surrogate; cells the gate accepts are
  * updated in place and flagged CHEM_FLAG_SURROGATE (flags is device in/out
  * and required; zero-fill it when no mapping is used), all other cells are
@@ -416,14 +417,15 @@ int chem_autotune(chem_ctx *ctx, int64_t n_cells, const double *T, const double 
 void chem_autotune_forget(void);
 
 /* Evaluate f(y) and the analytic Jacobian for n cells (kernel-level check of
- * the rate and Jacobian code of the integrator).  T, p [n], Y [N*n] device;
+ * the rate and Jacobian code of the integrator: the chemistry model of
+ * Sec. 2.1, the analytic Jacobian Sec. 5 names).  T, p [n], Y [N*n] device;
  * f [(N+1)*n] device out (row-major per cell: f[i*(N+1) + r]),
  * J [(N+1)^2 * n] device out (row-major per cell), either nullable. */
 int chem_eval_rhs_jac(chem_ctx *ctx, int64_t n_cells, const double *T, const double *p,
                       const double *Y, double *f, double *J);
 
 /* One Rodas4 step of fixed size h per cell with the analytic Jacobian
- * (no step control): y_new and the embedded error estimate, both
+ * (no step control; the implicit per-cell integration of Sec. 1): y_new and the embedded error estimate, both
  * [(N+1)*n] device out, row-major per cell. */
 int chem_rodas_step(chem_ctx *ctx, int64_t n_cells, const double *T, const double *p,
                     const double *Y, double h, double *ynew, double *err);
