@@ -35,9 +35,15 @@ class OStats(C.Structure):
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
-            build()
-        L = C.CDLL(LIB)
+        # ORACLE_LIB names another build of these sources (the mutation tests
+        # load deliberately broken copies through it); by default the library
+        # next to this file, built on first use
+        path = os.environ.get("ORACLE_LIB", "")
+        if not path:
+            path = LIB
+            if not os.path.exists(LIB):
+                build()
+        L = C.CDLL(path)
         L.orc_mech_create.restype = C.c_int
         L.orc_map_reference.restype = C.c_int64
         L.orc_enthalpy_mass.restype = C.c_double

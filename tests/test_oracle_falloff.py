@@ -3,7 +3,8 @@
 The fall-off factor G multiplies the high-pressure rate constant, G = Pr/(1+Pr) F
 with Pr = k0 [M] / k_inf.  Pinned against its limits (low pressure: k -> k0 [M];
 high pressure: k -> k_inf), Troe's broadening F between Fcent and 1, the centre of the
-Troe curve (log10 Pr = -c makes f1 = 0, so F = Fcent), Fcent = 1 reducing Troe
+Troe curve (log10 Pr = -c makes f1 = 0, so F = Fcent), the two points of half
+broadening (f1 = +-1, solved by hand), Fcent = 1 reducing Troe
 to Lindemann, monotonicity in [M], and through the whole
 right-hand side: central finite differences of the complex-step Jacobian,
 element and mass conservation, and the invariants of an integration."""
@@ -67,6 +68,48 @@ def test_troe_centre_and_limits(fo):
                 P = 10.0 ** e
                 F = fo.falloff_factor(j, T, P * kinf / k0) / (P / (1 + P))
                 assert Fc * (1 - 1e-12) <= F <= 1.0 + 1e-12
+
+
+def test_troe_half_broadening_points(fo):
+    """Where the broadening is half its centre value (log10 F = log10 Fcent / 2)
+    the Troe form has f1 = +-1, which, solved by hand for x = log10 Pr + c,
+    gives x = n / (1 + d) above the centre and x = -n / (1 - d) below it
+    (d = 0.14): the curve is narrower on the high-pressure side.  Both points
+    are found by bisection on the oracle's fall-off factor and compared with
+    these closed forms, which pins the centre c, the width n and the
+    asymmetry d together."""
+    mech = fo.mech
+    d = 0.14
+    checked = 0
+    for j in _reactions(mech, 2)[:8]:
+        for T in (500.0, 1200.0, 2500.0):
+            kinf, k0 = _kinf_k0(mech, j, T)
+            Fc = _fcent(mech, j, T)
+            if not (1e-3 < Fc < 0.9):
+                continue
+            lFc = np.log10(Fc)
+            c, n = -0.4 - 0.67 * lFc, 0.75 - 1.27 * lFc
+
+            def phi(x):   # log10 F / log10 Fcent at log10 Pr = x - c
+                P = 10.0 ** (x - c)
+                F = fo.falloff_factor(j, T, P * kinf / k0) / (P / (1 + P))
+                return np.log10(F) / lFc
+
+            def half(lo, hi):   # phi(lo) > 1/2 > phi(hi), phi monotone between
+                for _ in range(200):
+                    mid = 0.5 * (lo + hi)
+                    if phi(mid) > 0.5:
+                        lo = mid
+                    else:
+                        hi = mid
+                return 0.5 * (lo + hi)
+
+            x_up = half(0.0, 0.99 * n / d)
+            x_dn = half(0.0, -20.0)
+            assert x_up == pytest.approx(n / (1 + d), rel=1e-9, abs=1e-10)
+            assert x_dn == pytest.approx(-n / (1 - d), rel=1e-9, abs=1e-10)
+            checked += 1
+    assert checked >= 4
 
 
 def test_troe_with_unit_fcent_is_lindemann():
