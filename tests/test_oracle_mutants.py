@@ -57,6 +57,23 @@ MUTANTS = {
     "troe-centre-constant": (
         "rhs_body.h", "const SC c = -0.4 - 0.67 * lFc", "const SC c = -0.4 - 0.76 * lFc",
         ["tests/test_oracle_falloff.py"]),
+    "enthalpy-polynomial-term": (
+        "chem.c", "+ a[4] * T * T * T * T / 5.0 + a[5] / T;", "+ a[4] * T * T * T * T / 4.0 + a[5] / T;",
+        [PINS]),
+    "entropy-log-term": (
+        "chem.c", "s_R[k] = a[0] * lnT + a[1] * T", "s_R[k] = a[0] * T + a[1] * T", [PINS]),
+    "jacobian-heat-capacity-derivative": (
+        "chem.c", "return a[1] + 2.0 * a[2] * T + 3.0 * a[3] * T * T + 4.0 * a[4] * T * T * T;",
+        "return a[1] + 2.0 * a[2] * T + 2.0 * a[3] * T * T + 4.0 * a[4] * T * T * T;", [PINS]),
+    "error-norm-scale-ignores-new-state": (
+        "rodas.c", "double sc = o->atol + o->rtol * fmax(fabs(y[i]), fabs(ynew[i]));",
+        "double sc = o->atol + o->rtol * fabs(y[i]);", [PINS]),
+    "gelu-derivative": (
+        "mlp.c", "z * exp(-0.5 * z * z) / sqrt(2.0 * M_PI)", "z * exp(-z * z) / sqrt(2.0 * M_PI)",
+        ["tests/test_oracle_surrogate.py"]),
+    "gate-residual-sign": (
+        "mlp.c", "if (!(fabs(*T + dT - Th) <= tau_T)) return 0;",
+        "if (!(fabs(*T - dT - Th) <= tau_T)) return 0;", ["tests/test_oracle_surrogate.py"]),
     "plog-interpolation-end-swapped": (
         "rhs_body.h",
         "const double w = (log(p) - log(t[4 * i])) / (log(t[4 * i + 4]) - log(t[4 * i]));",

@@ -407,3 +407,33 @@ def test_status_codes(small):
     assert st.status == 1
     _, _, st = small.integrate_cell(P_ATM, y, 1e-6, hmin_frac=0.5)
     assert st.status == 2
+
+
+def test_step_acceptance_follows_the_error_norm(m53):
+    """One attempt of size h from a hot mixture with a few species absent: its
+    embedded error estimate (the separately pinned single step) measured as
+    max_i |err_i| / (atol + rtol max(|y_i|, |ynew_i|)) must decide acceptance
+    exactly at 1.  With atol negligible, rtol* = max_i |err_i| / max(|y_i|,
+    |ynew_i|) puts the norm at 1: the attempt is accepted at 1.001 rtol* and
+    rejected at 0.999 rtol* (a single allowed attempt ends with status 1)."""
+    mech = m53.mech
+    f = synth.field_mapped(400, seed=4)
+    i = int(np.nonzero(f.cls == 2)[0][0]) if np.any(f.cls == 2) else int(np.argmax(f.T))
+    Y = f.Y[:, i].copy()
+    Y[np.argsort(Y)[:5]] = 0.0          # absent species that the step produces
+    Y /= Y.sum()
+    y = np.concatenate([[f.T[i]], Y])
+    h = 1e-8
+    ynew, err, rc = m53.rodas4_step(P_ATM, y, h)
+    assert rc == 0
+    s = np.maximum(np.abs(y), np.abs(ynew))
+    live = s > 0.0
+    assert np.all(err[~live] == 0.0)
+    rtol_star = float(np.max(np.abs(err[live]) / s[live]))
+    assert 1e-14 < rtol_star < 1.0
+    _, _, st = m53.integrate_cell(P_ATM, y, h, h0=h, rtol=1.001 * rtol_star, atol=1e-300,
+                                  max_steps=1)
+    assert st.status == 0 and st.n_accept == 1 and st.n_reject == 0
+    _, _, st = m53.integrate_cell(P_ATM, y, h, h0=h, rtol=0.999 * rtol_star, atol=1e-300,
+                                  max_steps=1)
+    assert st.status == 1 and st.n_accept == 0 and st.n_reject == 1

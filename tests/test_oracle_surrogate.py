@@ -299,6 +299,32 @@ def test_gate_residual_threshold_tau_T():
     assert_reject(run_gate(o, P, p, T, Y, tau_T=dT - 1e-6), T, Y)
 
 
+def test_gate_residual_with_a_changed_composition():
+    """Mass moved between two species (dY != 0), so the conserved state Y'
+    has another enthalpy-temperature relation and T' differs from T.  The
+    gate's residual is then |T + dT - T'| with T' the temperature at which Y'
+    holds the input's enthalpy; it is rebuilt here from the separately pinned
+    conservation and enthalpy inversion, and the threshold must fall exactly
+    there (accept just above, reject just below), the accepted state being
+    (T', Y')."""
+    o, P, nb, p, T, Y, dT, N = gate_setup(0.3)
+    a, b = (int(k) for k in np.argsort(Y)[-2:])
+    for k, delta in ((a, -1e-3), (b, 1e-3)):
+        nb[2][k] = np.float32(np.arcsinh(delta / 1e-12))
+    dY = np.zeros(N)
+    for k in (a, b):
+        dY[k] = 1e-12 * np.sinh(float(nb[2][k]))
+    Yc = oracle.conserve(o, Y, np.maximum(Y + dY, 0.0))
+    assert Yc is not None
+    Tp, _ = o.temperature_from_enthalpy(o.enthalpy(T, Y), Yc, T + dT)
+    r = abs(T + dT - Tp)
+    # the composition change moves T' by far more than the threshold window below
+    assert abs(Tp - T) > 100 * 1e-6 * r
+    ok, T1, Y1 = run_gate(o, P, p, T, Y, tau_T=r * (1 + 1e-6))
+    assert ok and T1 == Tp and np.array_equal(Y1, Yc)
+    assert_reject(run_gate(o, P, p, T, Y, tau_T=r * (1 - 1e-6)), T, Y)
+
+
 def test_gate_predicted_dT_threshold():
     o, P, _, p, T, Y, dT, _ = gate_setup(0.3)
     assert_accept(run_gate(o, P, p, T, Y, max_dT=dT * (1 + 1e-9)), T, Y)
