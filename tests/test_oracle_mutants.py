@@ -68,6 +68,15 @@ MUTANTS = {
     "error-norm-scale-ignores-new-state": (
         "rodas.c", "double sc = o->atol + o->rtol * fmax(fabs(y[i]), fabs(ynew[i]));",
         "double sc = o->atol + o->rtol * fabs(y[i]);", [PINS]),
+    "controller-safety-factor": (
+        "rodas.c", "fmin(5.0, fmax(0.2, 0.9 * pow(e, -0.25)))", "fmin(5.0, fmax(0.2, 0.8 * pow(e, -0.25)))",
+        [PINS]),
+    "controller-growth-bound": (
+        "rodas.c", "fmin(5.0, fmax(0.2, 0.9 * pow(e, -0.25)))", "fmin(4.0, fmax(0.2, 0.9 * pow(e, -0.25)))",
+        [PINS]),
+    "controller-exponent": (
+        "rodas.c", "fmin(5.0, fmax(0.2, 0.9 * pow(e, -0.25)))", "fmin(5.0, fmax(0.2, 0.9 * pow(e, -0.2)))",
+        [PINS]),
     "gelu-derivative": (
         "mlp.c", "z * exp(-0.5 * z * z) / sqrt(2.0 * M_PI)", "z * exp(-z * z) / sqrt(2.0 * M_PI)",
         ["tests/test_oracle_surrogate.py"]),

@@ -437,3 +437,29 @@ def test_step_acceptance_follows_the_error_norm(m53):
     _, _, st = m53.integrate_cell(P_ATM, y, h, h0=h, rtol=0.999 * rtol_star, atol=1e-300,
                                   max_steps=1)
     assert st.status == 1 and st.n_accept == 0 and st.n_reject == 1
+
+
+def test_step_size_proposal_follows_the_controller(m53):
+    """After one accepted attempt the proposed next step is
+    h min(5, max(0.2, 0.9 err^(-1/4))) with err the max-norm of the separately
+    computed error estimate: checked where the factor is inside its bounds
+    (err = 0.1 and 0.5) and where the growth bound of 5 holds (err = 1e-8)."""
+    mech = m53.mech
+    f = synth.field_mapped(400, seed=4)
+    i = int(np.nonzero(f.cls == 2)[0][0])
+    y = np.concatenate([[f.T[i]], f.Y[:, i]])
+    h = 1e-8
+    ynew, err, rc = m53.rodas4_step(P_ATM, y, h)
+    assert rc == 0
+    s = np.maximum(np.abs(y), np.abs(ynew))
+    live = s > 0.0
+    rtol_star = float(np.max(np.abs(err[live]) / s[live]))
+    for e_target in (0.5, 0.1, 1e-8):
+        rtol = rtol_star / e_target
+        e = float(np.max(np.abs(err) / (1e-300 + rtol * s)))
+        _, h_next, st = m53.integrate_cell(P_ATM, y, h, h0=h, rtol=rtol, atol=1e-300, max_steps=1)
+        assert st.status == 0 and st.n_accept == 1
+        want = h * min(5.0, max(0.2, 0.9 * e ** -0.25))
+        assert h_next == pytest.approx(want, rel=1e-13)
+        if e_target == 1e-8:
+            assert h_next == pytest.approx(5.0 * h, rel=1e-15)
